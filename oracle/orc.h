@@ -1,0 +1,92 @@
+/*
+ * orc.h -- plain FP64 CPU oracle for the DGSEM compressible-Euler right-hand side.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and
+ * its Python binding) may include, link or call this code; only the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark do.  The oracle shares
+ * no source with the HIP path.
+ *
+ * What it computes (paper: Trixi.jl, arXiv 2108.06476):
+ *   - the semidiscretisation of the conservation law of Eq. (1) (Section 2)
+ *     for the ideal-gas Euler equations, no source term, by the nodal DGSEM on
+ *     Legendre-Gauss-Lobatto nodes (Section 2.1, "matrix-free DG methods"),
+ *   - with the flux-differencing volume integral and an entropy-conservative,
+ *     kinetic-energy-preserving two-point flux (Section 3.1), or a central
+ *     volume flux, or the weak form (Section 3.1: central volume flux == weak
+ *     form), or the Hennemann-Gassner blended DG/FV shock-capturing volume
+ *     integral (Section 2.1, "entropy-stable sub-cell shock capturing"),
+ *   - LLF / HLL / EC interface fluxes (Sections 2.3.1 and 3.1),
+ *   - the Carpenter-Kennedy five-stage fourth-order low-storage Runge-Kutta
+ *     method with the CFL time step of Section 3.1.
+ * Every evaluation is straightforward FP64 loops, compiled without FMA
+ * contraction (the appendix discusses contraction; the oracle keeps every
+ * product and sum rounded separately).
+ *
+ * Layout of every state array: u[var][elem][node], FP64, var in
+ * (rho, rho v_1 .. rho v_dim, rho E); node = i + n*(j + n*k) with n = N+1 and
+ * i along x; elem = ex + Kx*(ey + Ky*ez).  All arrays are caller-owned host
+ * memory.  Functions return ORC_OK (0) or a positive error code.
+ */
+#ifndef ORC_H
+#define ORC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_ENONPHYS = 4 };
+enum { ORC_VOL_EC = 0, ORC_VOL_CENTRAL = 1, ORC_VOL_SHOCKCAP_HG = 2, ORC_VOL_WEAK = 3,
+       ORC_VOL_NONE = 4 };
+enum { ORC_SURF_LLF = 0, ORC_SURF_HLL = 1, ORC_SURF_EC = 2, ORC_SURF_NONE = 3 };
+
+#define ORC_MAXN 15   /* polynomial degrees 3..15 as in the PID study (Section 3.1) */
+
+typedef struct {
+  int32_t dim;        /* 2 or 3 */
+  int32_t polydeg;    /* N, 1 <= N <= ORC_MAXN */
+  int32_t cells[3];   /* elements per direction, periodic; cells[2] = 1 in 2D */
+  double  xmin[3], xmax[3];
+  double  gamma;
+  int32_t volume;     /* ORC_VOL_* */
+  int32_t surface;    /* ORC_SURF_* */
+  int32_t fv_flux;    /* ORC_SURF_LLF or ORC_SURF_HLL: subcell FV flux */
+  double  alpha_max;  /* shock capturing: upper clip of alpha */
+  double  alpha_min;  /* shock capturing: alpha below this -> 0, above 1-this -> 1 */
+  int32_t alpha_smooth; /* 1: neighbour smoothing of alpha */
+} orc_config;
+
+/* LGL nodes x[N+1], weights w[N+1], differentiation matrix D[(N+1)*(N+1)] (row-major,
+ * D[i*(N+1)+j] = l_j'(x_i)). */
+int orc_lgl(int N, double *x, double *w, double *D);
+/* Inverse of the orthonormal-Legendre Vandermonde matrix V_ia = Lt_a(x_i). */
+int orc_legendre_vinv(int N, double *Vinv);
+
+/* Pointwise physics (direction d in 0..dim-1).  u, fL/fR/f have dim+2 entries. */
+double orc_ln_mean(double x, double y);
+int orc_flux_phys(const double *u, int d, int dim, double gamma, double *f);
+int orc_flux_ec(const double *uL, const double *uR, int d, int dim, double gamma, double *f);
+int orc_flux_central(const double *uL, const double *uR, int d, int dim, double gamma, double *f);
+int orc_flux_llf(const double *uL, const double *uR, int d, int dim, double gamma, double *f);
+int orc_flux_hll(const double *uL, const double *uR, int d, int dim, double gamma, double *f);
+/* entropy S(u) and entropy variables w(u) */
+double orc_entropy(const double *u, int dim, double gamma);
+int orc_entropy_vars(const double *u, int dim, double gamma, double *w);
+
+int64_t orc_num_nodes(const orc_config *cfg);
+int orc_node_coords(const orc_config *cfg, double *xyz);            /* [dim][E][n^dim] */
+int orc_rhs(const orc_config *cfg, const double *u, double *du);
+int orc_indicator(const orc_config *cfg, const double *u, double *alpha_raw, double *alpha);
+int orc_indicator_energy(const orc_config *cfg, const double *u, double *energy); /* [E] */
+int orc_rhs_alpha(const orc_config *cfg, const double *u, const double *alpha, double *du);
+int orc_max_dt(const orc_config *cfg, const double *u, double cfl, double *dt);
+int orc_lsrk_coeffs(double *A, double *B, double *c);
+int orc_step(const orc_config *cfg, double *u, int32_t nsteps, double cfl, double dt_fixed,
+             double *t);
+int orc_integrals(const orc_config *cfg, const double *u, const double *du, double *out7);
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
