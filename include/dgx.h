@@ -1,0 +1,176 @@
+/*
+ * dgx.h -- C ABI of the MI355X (gfx950) DGSEM compressible-Euler right-hand side.
+ *
+ * The method is the semidiscretisation of Trixi.jl (arXiv 2108.06476): the
+ * conservation law of Eq. (1) for the ideal-gas Euler equations (no source term)
+ * discretised by the nodal DGSEM on Legendre-Gauss-Lobatto nodes (Section 2.1)
+ * on a uniform, periodic Cartesian quad/hex grid (the TreeMesh of Section 2.3.1
+ * at uniform refinement), with
+ *   - the flux-differencing volume integral with an entropy-conservative,
+ *     kinetic-energy-preserving two-point flux, or a central volume flux
+ *     (equal to the weak form, Section 3.1),
+ *   - LLF / HLL / EC interface fluxes (Sections 2.3.1 and 3.1),
+ *   - the surface lift and the Cartesian Jacobian 2/h,
+ *   - the entropy-stable subcell shock capturing of Section 2.1
+ *     (Hennemann-Gassner indicator, blended DG/FV volume integral),
+ *   - the Carpenter-Kennedy five-stage fourth-order low-storage Runge-Kutta
+ *     method with the adaptive CFL time step of Section 3.1.
+ * Every step runs in hand-written HIP kernels on the GPU.
+ *
+ * Conventions for every call:
+ *   - State layout: u[var][elem][node], float64, contiguous (structure of
+ *     arrays); var = (rho, rho v_1 .. rho v_dim, rho E); node = i + n*(j + n*k)
+ *     with n = N+1 and i along x; elem = ex + Kx*(ey + Ky*ez).  Element e spans
+ *     [xmin + e h, xmin + (e+1) h] per direction; its node i sits at
+ *     xmin + e h + (h/2)(1 + x_i), x_i the LGL nodes.
+ *   - Every array argument is a caller-owned DEVICE pointer, borrowed only for
+ *     the work enqueued by the call.  Host pointers are named as such.
+ *   - All work is enqueued asynchronously on the handle's HIP stream; only
+ *     dgx_check() and dgx_last_error() synchronise or read host state.  The
+ *     library allocates device scratch at create time and frees it at destroy.
+ *   - Calls return a dgx_status.  Argument errors are detected on the host and
+ *     returned at once (nothing is enqueued); a non-physical state met by a
+ *     kernel (rho <= 0, p <= 0 or NaN) raises a device flag read by dgx_check().
+ *   - There is no global state: handles are independent (Section 2.3.3) and may
+ *     be used from different host threads; one handle is not thread-safe.
+ */
+#ifndef DGX_H
+#define DGX_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DGX_OK = 0,
+  DGX_EINVAL = 1,        /* bad argument or configuration */
+  DGX_EHIP = 2,          /* a HIP runtime call failed (see dgx_last_error) */
+  DGX_ENOMEM = 3,        /* device allocation failed */
+  DGX_ENONPHYS = 4,      /* a kernel met a non-physical state */
+  DGX_EUNSUPPORTED = 5   /* valid but not built (e.g. polydeg outside the compiled set) */
+} dgx_status;
+
+typedef enum {
+  DGX_VOL_EC = 0,          /* flux differencing, entropy-conservative two-point flux */
+  DGX_VOL_CENTRAL = 1,     /* flux differencing, central flux (= weak form) */
+  DGX_VOL_SHOCKCAP_HG = 2, /* blended: (1-alpha) EC flux differencing + alpha FV */
+  DGX_VOL_NONE = 4         /* no volume term (testing: surface terms only) */
+} dgx_volume;
+
+typedef enum {
+  DGX_SURF_LLF = 0,
+  DGX_SURF_HLL = 1,
+  DGX_SURF_EC = 2,
+  DGX_SURF_NONE = 3        /* no surface term (testing: volume term only) */
+} dgx_surface;
+
+typedef enum {
+  DGX_FP64 = 0,            /* every operation in float64 */
+  DGX_MIXED = 1            /* volume two-point fluxes and volume sums in float32;
+                              near-equal-state log means, interface fluxes, RK
+                              accumulation and reductions in float64 */
+} dgx_precision;
+
+typedef struct {
+  int32_t dim;            /* 2 or 3 */
+  int32_t polydeg;        /* N; compiled for 1..7 (3D) and 1..7 (2D) */
+  int32_t cells[3];       /* elements per direction, periodic; cells[2] = 1 in 2D */
+  double  xmin[3], xmax[3];
+  double  gamma;          /* ratio of specific heats, > 1 */
+  int32_t volume;         /* dgx_volume */
+  int32_t surface;        /* dgx_surface */
+  int32_t fv_flux;        /* DGX_SURF_LLF or DGX_SURF_HLL: subcell FV flux */
+  double  alpha_max;      /* shock capturing: upper clip of alpha (e.g. 0.5) */
+  double  alpha_min;      /* alpha < alpha_min -> 0, alpha > 1 - alpha_min -> 1 (e.g. 0.001) */
+  int32_t alpha_smooth;   /* 1: alpha_e = max(alpha_e, max_neighbours alpha_nb / 2) */
+  int32_t precision;      /* dgx_precision */
+} dgx_config;
+
+typedef struct dgx_solver *dgx_handle;
+
+/* Create a solver for cfg (host pointer, copied) whose work goes to hip_stream
+ * (a hipStream_t; NULL = the null stream).  Allocates the device scratch. */
+dgx_status dgx_create(const dgx_config *cfg, void *hip_stream, dgx_handle *out);
+dgx_status dgx_destroy(dgx_handle h);
+/* Re-target the handle's work to another stream (e.g. the caller's current one). */
+dgx_status dgx_set_stream(dgx_handle h, void *hip_stream);
+
+/* E * (N+1)^dim: nodes per variable. */
+int64_t dgx_num_nodes(dgx_handle h);
+int64_t dgx_num_elements(dgx_handle h);
+
+/* Node coordinates, device xyz[dim][E][n^dim] (the layout above). */
+dgx_status dgx_node_coords(dgx_handle h, double *xyz);
+
+/* du = R(u): the semidiscrete right-hand side du/dt (Eq. (1) discretised).  u, du
+ * are device [nvar][E][n^dim] and must not overlap.  For DGX_VOL_SHOCKCAP_HG the
+ * indicator is evaluated from u first.  t is unused (no source terms). */
+dgx_status dgx_rhs(dgx_handle h, const double *u, double *du, double t);
+
+/* Hennemann-Gassner indicator of u: alpha[E] (device), clipped and, when
+ * cfg.alpha_smooth, smoothed.  alpha_raw (device, may be NULL) receives the
+ * unsmoothed clipped values; energy (device, may be NULL) the modal energy ratio. */
+dgx_status dgx_indicator(dgx_handle h, const double *u, double *alpha, double *alpha_raw,
+                         double *energy);
+
+/* du = R(u) with the blending factors alpha[E] (device) given instead of computed
+ * (DGX_VOL_SHOCKCAP_HG only). */
+dgx_status dgx_rhs_alpha(dgx_handle h, const double *u, const double *alpha, double *du);
+
+/* dt = cfl * 2 / ((N+1) max_e sum_d (2/h_d) max_nodes(|v_d| + c)), written to the
+ * device scalar *dt (Section 3.1: local wave speed, relative grid size, CFL). */
+dgx_status dgx_max_dt(dgx_handle h, const double *u, double cfl, double *dt);
+
+/* Advance u in place by nsteps Carpenter-Kennedy 5-stage 4th-order 2N-storage
+ * steps: per step dt from u at its start (cfl > 0) or dt_fixed (cfl <= 0), then
+ * for s = 1..5: k <- A_s k + dt R(u), u <- u + B_s k.  t (device scalar, may be
+ * NULL) is advanced by every dt.  The stage register lives in library scratch. */
+dgx_status dgx_step(dgx_handle h, double *u, int32_t nsteps, double cfl, double dt_fixed,
+                    double *t);
+
+/* out7 (device, 7 doubles): [0..dim+1] = sum J w u_v, [5] = sum J w S(u) with
+ * S = -rho s/(gamma-1), s = ln p - gamma ln rho, [6] = sum J w w(u).du (0 when du
+ * is NULL), J = prod h_d/2.  Deterministic order. */
+dgx_status dgx_integrals(dgx_handle h, const double *u, const double *du, double *out7);
+
+/* Synchronise the stream and report (and clear) the non-physical-state flag:
+ * *flag = 1 if any kernel since the last check met rho <= 0, p <= 0 or NaN. */
+dgx_status dgx_check(dgx_handle h, int32_t *flag);
+
+/* The handle's last error message (host string owned by the handle). */
+const char *dgx_last_error(dgx_handle h);
+
+/* Kernel timing of the last dgx_rhs / dgx_step launch sequence, for benchmarks:
+ * enables HIP-event timing of the dominant kernel on the handle's stream. */
+dgx_status dgx_profile_enable(dgx_handle h, int32_t on);
+/* Average duration in milliseconds of the timed kernel's launches since enable, and
+ * its name (host string). */
+dgx_status dgx_profile_read(dgx_handle h, double *avg_ms, int64_t *launches, const char **name);
+
+/* ----- ensembles: many independent solvers advanced together ----- */
+typedef struct dgx_batch_s *dgx_batch;
+
+/* nruns configurations (host array, copied); every run is 3D, DGX_VOL_EC,
+ * DGX_SURF_LLF or HLL, with its own grid and polydeg; all share one precision. */
+dgx_status dgx_batch_create(const dgx_config *cfgs, int32_t nruns, void *hip_stream,
+                            dgx_batch *out);
+dgx_status dgx_batch_destroy(dgx_batch b);
+/* number of nodes of run r (per variable) */
+int64_t dgx_batch_num_nodes(dgx_batch b, int32_t r);
+/* Advance every run by nsteps, each with its own dt from its own state (cfl > 0).
+ * u: host array of nruns device pointers, each [5][E_r][n_r^3].  t: device [nruns]
+ * (may be NULL). */
+dgx_status dgx_batch_step(dgx_batch b, double *const *u, int32_t nsteps, double cfl,
+                          double *t);
+/* du_r = R_r(u_r) for every run (host arrays of device pointers). */
+dgx_status dgx_batch_rhs(dgx_batch b, const double *const *u, double *const *du);
+/* Pick the work-item tile shape by timing the candidates on the current states.
+ * budget_ms bounds the tuning time; the choice is kept in the batch. */
+dgx_status dgx_batch_tune(dgx_batch b, double *const *u, int32_t budget_ms);
+const char *dgx_batch_last_error(dgx_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

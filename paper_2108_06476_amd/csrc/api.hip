@@ -1,0 +1,504 @@
+// api.hip -- the dgx C ABI (include/dgx.h): handle management, argument checks and the
+// launch sequences of the right-hand side, the indicator, the CFL time step, the
+// low-storage Runge-Kutta step and the integrals.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dgx.h"
+#include "registry.h"
+#include "tables.h"
+
+namespace dgx {
+const Launchers* launchers_d2_n1();
+const Launchers* launchers_d2_n2();
+const Launchers* launchers_d2_n3();
+const Launchers* launchers_d2_n4();
+const Launchers* launchers_d2_n5();
+const Launchers* launchers_d2_n6();
+const Launchers* launchers_d2_n7();
+const Launchers* launchers_d3_n1();
+const Launchers* launchers_d3_n2();
+const Launchers* launchers_d3_n3();
+const Launchers* launchers_d3_n4();
+const Launchers* launchers_d3_n5();
+const Launchers* launchers_d3_n6();
+const Launchers* launchers_d3_n7();
+
+const Launchers* launchers_2d(int N) {
+  switch (N) {
+    case 1: return launchers_d2_n1();
+    case 2: return launchers_d2_n2();
+    case 3: return launchers_d2_n3();
+    case 4: return launchers_d2_n4();
+    case 5: return launchers_d2_n5();
+    case 6: return launchers_d2_n6();
+    case 7: return launchers_d2_n7();
+    default: return nullptr;
+  }
+}
+
+const Launchers* launchers_3d(int N) {
+  switch (N) {
+    case 1: return launchers_d3_n1();
+    case 2: return launchers_d3_n2();
+    case 3: return launchers_d3_n3();
+    case 4: return launchers_d3_n4();
+    case 5: return launchers_d3_n5();
+    case 6: return launchers_d3_n6();
+    case 7: return launchers_d3_n7();
+    default: return nullptr;
+  }
+}
+
+// Carpenter-Kennedy (1994) five-stage fourth-order 2N-storage coefficients (the time
+// integrator of Section 3.1): k <- A_s k + dt R, u <- u + B_s k.
+static const double CK_A[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                               -2404267990393.0 / 2016746695238.0,
+                               -3550918686646.0 / 2091501179385.0,
+                               -1275806237668.0 / 842570457699.0};
+static const double CK_B[5] = {1432997174477.0 / 9575080441755.0,
+                               5161836677717.0 / 13612068292357.0,
+                               1720146321549.0 / 2090206949498.0,
+                               3134564353537.0 / 4481467310338.0,
+                               2277821191437.0 / 14882151754819.0};
+
+// dt = cfl * 2 / ((N+1) * max partial); t += dt
+__global__ __launch_bounds__(256) void k_dt_final(const double* __restrict__ partial, int64_t np,
+                                                  double cfl, double n1, double* __restrict__ dt,
+                                                  double* __restrict__ t) {
+  __shared__ double s[256];
+  double m = 0.0;
+  for (int64_t i = threadIdx.x; i < np; i += 256) m = fmax(m, partial[i]);
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double d = cfl * 2.0 / (n1 * s[0]);
+    *dt = d;
+    if (t) *t += d;
+  }
+}
+
+__global__ void k_set_dt(double v, double* __restrict__ dt, double* __restrict__ t) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *dt = v;
+    if (t) *t += v;
+  }
+}
+
+// out[c] = sum over blocks of partial[b*7 + c], fixed order
+__global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ partial, int64_t np,
+                                                   double* __restrict__ out) {
+  __shared__ double s[7][256];
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i = threadIdx.x; i < np; i += 256)
+    for (int c = 0; c < 7; ++c) acc[c] += partial[i * 7 + c];
+  for (int c = 0; c < 7; ++c) s[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int c = 0; c < 7; ++c) s[c][threadIdx.x] += s[c][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 7) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
+}
+
+}  // namespace dgx
+
+using namespace dgx;
+
+struct dgx_solver {
+  dgx_config cfg{};
+  int dim = 0, N = 0, n = 0, NN = 0, NF = 0, NV = 0;
+  int64_t E = 0;
+  double h[3] = {1, 1, 1};
+  hipStream_t stream = nullptr;
+  const Launchers* L = nullptr;
+  Geom g{};
+  double* tab = nullptr;
+  double* F = nullptr;
+  double* k = nullptr;
+  double* alpha = nullptr;
+  double* alpha_raw = nullptr;
+  double* energy = nullptr;
+  double* partial = nullptr;
+  int64_t npart = 0;
+  double* dt = nullptr;
+  int* flag = nullptr;
+  std::string err;
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  int64_t launches = 0;
+  double prof_ms = 0.0;
+};
+
+namespace {
+
+dgx_status fail(dgx_handle h, dgx_status st, const std::string& msg) {
+  if (h) h->err = msg;
+  return st;
+}
+
+#define HIPCHK(h, expr)                                                                \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(h, DGX_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+// A device array argument must lie inside one device allocation of at least `bytes`.
+dgx_status check_dev(dgx_handle h, const void* p, size_t bytes, const char* name) {
+  if (!p) return fail(h, DGX_EINVAL, std::string(name) + ": NULL pointer");
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, DGX_EINVAL, std::string(name) + ": not a device pointer");
+  }
+  if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+    return fail(h, DGX_EINVAL, std::string(name) + ": not device memory");
+  hipDeviceptr_t base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, DGX_EINVAL, std::string(name) + ": no allocation range");
+  }
+  const char* b = (const char*)base;
+  const char* q = (const char*)p;
+  if (q + bytes > b + size)
+    return fail(h, DGX_EINVAL, std::string(name) + ": allocation too small (" +
+                                   std::to_string(size - (size_t)(q - b)) + " < " +
+                                   std::to_string(bytes) + " bytes)");
+  return DGX_OK;
+}
+
+#define CHKDEV(h, p, bytes, name)                             \
+  do {                                                        \
+    dgx_status s_ = check_dev(h, p, bytes, name);             \
+    if (s_ != DGX_OK) return s_;                              \
+  } while (0)
+
+size_t state_bytes(dgx_handle h) { return sizeof(double) * (size_t)h->NV * h->E * h->NN; }
+
+// Optional event timing of the dominant (volume) kernel.
+hipError_t timed_volume(dgx_handle h, const VolArgs& a, int epi) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (h->prof) {
+    if (h->ev_used + 2 > h->ev.size()) {
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t ev;
+        hipError_t r = hipEventCreate(&ev);
+        if (r != hipSuccess) return r;
+        h->ev.push_back(ev);
+      }
+    }
+    e0 = h->ev[h->ev_used];
+    e1 = h->ev[h->ev_used + 1];
+    h->ev_used += 2;
+    hipError_t r = hipEventRecord(e0, h->stream);
+    if (r != hipSuccess) return r;
+  }
+  hipError_t r = h->L->volume(h->stream, a, h->g, h->cfg.volume, epi, h->cfg.fv_flux,
+                              h->cfg.precision);
+  if (r != hipSuccess) return r;
+  if (h->prof) r = hipEventRecord(e1, h->stream);
+  return r;
+}
+
+dgx_status enqueue_indicator(dgx_handle h, const double* u, double* alpha, double* ar,
+                             double* en) {
+  HIPCHK(h, h->L->indicator(h->stream, u, ar, en, h->g, h->cfg.alpha_min, h->cfg.alpha_max));
+  HIPCHK(h, h->L->smooth(h->stream, ar, alpha, h->g, h->cfg.alpha_smooth));
+  return DGX_OK;
+}
+
+// R(u) into `out` (RHS) or the RK stage update of u in place.
+dgx_status enqueue_rhs(dgx_handle h, const double* u, double* out, const double* alpha_in,
+                       int epi, double A, double B) {
+  const double* alpha = alpha_in;
+  if (h->cfg.volume == DGX_VOL_SHOCKCAP_HG && !alpha) {
+    dgx_status st = enqueue_indicator(h, u, h->alpha, h->alpha_raw, nullptr);
+    if (st != DGX_OK) return st;
+    alpha = h->alpha;
+  }
+  if (h->cfg.surface != DGX_SURF_NONE) HIPCHK(h, h->L->surface(h->stream, u, h->F, h->g, h->cfg.surface));
+  VolArgs a;
+  a.u = u;
+  a.out = out;
+  a.k = h->k;
+  a.F = h->cfg.surface != DGX_SURF_NONE ? h->F : nullptr;
+  a.alpha = alpha;
+  a.dt = h->dt;
+  a.A = A;
+  a.B = B;
+  HIPCHK(h, timed_volume(h, a, epi));
+  return DGX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dgx_status dgx_create(const dgx_config* cfg, void* hip_stream, dgx_handle* out) {
+  if (!cfg || !out) return DGX_EINVAL;
+  *out = nullptr;
+  const dgx_config& c = *cfg;
+  if (c.dim != 2 && c.dim != 3) return DGX_EINVAL;
+  if (c.polydeg < 1) return DGX_EINVAL;
+  if (!(c.gamma > 1.0)) return DGX_EINVAL;
+  for (int d = 0; d < c.dim; ++d)
+    if (c.cells[d] < 1 || !(c.xmax[d] > c.xmin[d])) return DGX_EINVAL;
+  if (c.dim == 2 && c.cells[2] != 1) return DGX_EINVAL;
+  if (c.volume != DGX_VOL_EC && c.volume != DGX_VOL_CENTRAL && c.volume != DGX_VOL_SHOCKCAP_HG &&
+      c.volume != DGX_VOL_NONE)
+    return c.volume == 3 ? DGX_EUNSUPPORTED : DGX_EINVAL;
+  if (c.surface < DGX_SURF_LLF || c.surface > DGX_SURF_NONE) return DGX_EINVAL;
+  if (c.volume == DGX_VOL_SHOCKCAP_HG) {
+    if (c.fv_flux != DGX_SURF_LLF && c.fv_flux != DGX_SURF_HLL) return DGX_EINVAL;
+    if (!(c.alpha_max >= 0.0 && c.alpha_max <= 1.0) || !(c.alpha_min >= 0.0 && c.alpha_min < 0.5))
+      return DGX_EINVAL;
+  }
+  if (c.precision != DGX_FP64 && c.precision != DGX_MIXED) return DGX_EINVAL;
+  if (c.precision == DGX_MIXED && c.volume != DGX_VOL_EC) return DGX_EUNSUPPORTED;
+  const Launchers* L = launchers(c.dim, c.polydeg);
+  if (!L) return DGX_EUNSUPPORTED;
+
+  dgx_handle h = new dgx_solver();
+  h->cfg = c;
+  h->dim = c.dim;
+  h->N = c.polydeg;
+  h->n = c.polydeg + 1;
+  h->NN = c.dim == 3 ? h->n * h->n * h->n : h->n * h->n;
+  h->NF = c.dim == 3 ? h->n * h->n : h->n;
+  h->NV = c.dim + 2;
+  h->E = 1;
+  for (int d = 0; d < 3; ++d) {
+    const int K = d < c.dim ? c.cells[d] : 1;
+    h->E *= K;
+    h->h[d] = d < c.dim ? (c.xmax[d] - c.xmin[d]) / K : 1.0;
+  }
+  h->stream = (hipStream_t)hip_stream;
+  h->L = L;
+
+  // operator tables
+  std::vector<double> T(TAB_SIZE, 0.0);
+  double x[16], w[16], D[256], Vinv[256];
+  if (!lgl_tables(h->N, x, w, D, Vinv)) {
+    delete h;
+    return DGX_EINVAL;
+  }
+  const int n = h->n;
+  for (int d = 0; d < 3; ++d) {
+    const double jac = 2.0 / h->h[d];
+    for (int i = 0; i < n; ++i)
+      for (int m = 0; m < n; ++m)
+        T[TAB_S + (d * TMAX + i) * TMAX + m] = (i == m) ? 0.0 : -jac * 2.0 * D[i * n + m];
+    T[TAB_LIFT + d * 2 + 0] = jac / w[0];
+    T[TAB_LIFT + d * 2 + 1] = -jac / w[h->N];
+    for (int i = 0; i < n; ++i) T[TAB_FV + d * TMAX + i] = -jac / w[i];
+    T[TAB_JAC + d] = jac;
+  }
+  for (int a = 0; a < n; ++a)
+    for (int i = 0; i < n; ++i) T[TAB_VINV + a * TMAX + i] = Vinv[a * n + i];
+  for (int i = 0; i < n; ++i) {
+    T[TAB_W + i] = w[i];
+    T[TAB_X + i] = x[i];
+  }
+
+  const int64_t nblk = (h->E + L->ne - 1) / L->ne;
+  h->npart = nblk;
+  auto alloc = [&](void** p, size_t bytes) -> bool {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return true;
+  };
+  bool ok = alloc((void**)&h->tab, sizeof(double) * TAB_SIZE) &&
+            alloc((void**)&h->F, sizeof(double) * (size_t)h->dim * h->NV * h->E * h->NF) &&
+            alloc((void**)&h->k, state_bytes(h)) &&
+            alloc((void**)&h->alpha, sizeof(double) * h->E) &&
+            alloc((void**)&h->alpha_raw, sizeof(double) * h->E) &&
+            alloc((void**)&h->energy, sizeof(double) * h->E) &&
+            alloc((void**)&h->partial, sizeof(double) * 7 * (size_t)nblk) &&
+            alloc((void**)&h->dt, sizeof(double) * 2) && alloc((void**)&h->flag, sizeof(int) * 2);
+  if (!ok) {
+    dgx_destroy(h);
+    return DGX_ENOMEM;
+  }
+  if (hipMemcpy(h->tab, T.data(), sizeof(double) * TAB_SIZE, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(h->k, 0, state_bytes(h)) != hipSuccess ||
+      hipMemset(h->alpha, 0, sizeof(double) * h->E) != hipSuccess ||
+      hipMemset(h->flag, 0, sizeof(int) * 2) != hipSuccess ||
+      hipMemset(h->dt, 0, sizeof(double) * 2) != hipSuccess) {
+    dgx_destroy(h);
+    return DGX_EHIP;
+  }
+  h->g.E = h->E;
+  for (int d = 0; d < 3; ++d) h->g.K[d] = d < c.dim ? c.cells[d] : 1;
+  h->g.gamma = c.gamma;
+  h->g.tab = h->tab;
+  h->g.flag = h->flag;
+  *out = h;
+  return DGX_OK;
+}
+
+dgx_status dgx_destroy(dgx_handle h) {
+  if (!h) return DGX_EINVAL;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  for (void* p : {(void*)h->tab, (void*)h->F, (void*)h->k, (void*)h->alpha, (void*)h->alpha_raw,
+                  (void*)h->energy, (void*)h->partial, (void*)h->dt, (void*)h->flag})
+    if (p) (void)hipFree(p);
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  delete h;
+  return DGX_OK;
+}
+
+dgx_status dgx_set_stream(dgx_handle h, void* hip_stream) {
+  if (!h) return DGX_EINVAL;
+  h->stream = (hipStream_t)hip_stream;
+  return DGX_OK;
+}
+
+int64_t dgx_num_nodes(dgx_handle h) { return h ? h->E * h->NN : -1; }
+int64_t dgx_num_elements(dgx_handle h) { return h ? h->E : -1; }
+
+dgx_status dgx_node_coords(dgx_handle h, double* xyz) {
+  if (!h) return DGX_EINVAL;
+  CHKDEV(h, xyz, sizeof(double) * (size_t)h->dim * h->E * h->NN, "xyz");
+  HIPCHK(h, h->L->coords(h->stream, xyz, h->g, h->cfg.xmin));
+  return DGX_OK;
+}
+
+dgx_status dgx_rhs(dgx_handle h, const double* u, double* du, double t) {
+  (void)t;
+  if (!h) return DGX_EINVAL;
+  CHKDEV(h, u, state_bytes(h), "u");
+  CHKDEV(h, du, state_bytes(h), "du");
+  if (u == du) return fail(h, DGX_EINVAL, "u and du must not overlap");
+  return enqueue_rhs(h, u, du, nullptr, EPI_RHS, 0.0, 0.0);
+}
+
+dgx_status dgx_rhs_alpha(dgx_handle h, const double* u, const double* alpha, double* du) {
+  if (!h) return DGX_EINVAL;
+  if (h->cfg.volume != DGX_VOL_SHOCKCAP_HG)
+    return fail(h, DGX_EINVAL, "dgx_rhs_alpha needs DGX_VOL_SHOCKCAP_HG");
+  CHKDEV(h, u, state_bytes(h), "u");
+  CHKDEV(h, du, state_bytes(h), "du");
+  CHKDEV(h, alpha, sizeof(double) * h->E, "alpha");
+  if (u == du) return fail(h, DGX_EINVAL, "u and du must not overlap");
+  return enqueue_rhs(h, u, du, alpha, EPI_RHS, 0.0, 0.0);
+}
+
+dgx_status dgx_indicator(dgx_handle h, const double* u, double* alpha, double* alpha_raw,
+                         double* energy) {
+  if (!h) return DGX_EINVAL;
+  CHKDEV(h, u, state_bytes(h), "u");
+  CHKDEV(h, alpha, sizeof(double) * h->E, "alpha");
+  if (alpha_raw) CHKDEV(h, alpha_raw, sizeof(double) * h->E, "alpha_raw");
+  if (energy) CHKDEV(h, energy, sizeof(double) * h->E, "energy");
+  if (alpha_raw == alpha) return fail(h, DGX_EINVAL, "alpha and alpha_raw must differ");
+  return enqueue_indicator(h, u, alpha, alpha_raw ? alpha_raw : h->alpha_raw, energy);
+}
+
+dgx_status dgx_max_dt(dgx_handle h, const double* u, double cfl, double* dt) {
+  if (!h) return DGX_EINVAL;
+  if (!(cfl > 0.0)) return fail(h, DGX_EINVAL, "cfl must be > 0");
+  CHKDEV(h, u, state_bytes(h), "u");
+  CHKDEV(h, dt, sizeof(double), "dt");
+  HIPCHK(h, h->L->maxspeed(h->stream, u, h->partial, h->g));
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, h->stream, h->partial, h->npart, cfl,
+                     (double)(h->N + 1), dt, (double*)nullptr);
+  HIPCHK(h, hipGetLastError());
+  return DGX_OK;
+}
+
+dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double dt_fixed,
+                    double* t) {
+  if (!h) return DGX_EINVAL;
+  if (nsteps < 0) return fail(h, DGX_EINVAL, "nsteps < 0");
+  if (!(cfl > 0.0) && !(dt_fixed > 0.0)) return fail(h, DGX_EINVAL, "need cfl > 0 or dt_fixed > 0");
+  CHKDEV(h, u, state_bytes(h), "u");
+  if (t) CHKDEV(h, t, sizeof(double), "t");
+  for (int s = 0; s < nsteps; ++s) {
+    if (cfl > 0.0) {
+      HIPCHK(h, h->L->maxspeed(h->stream, u, h->partial, h->g));
+      hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, h->stream, h->partial, h->npart, cfl,
+                         (double)(h->N + 1), h->dt, t);
+    } else {
+      hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, h->stream, dt_fixed, h->dt, t);
+    }
+    HIPCHK(h, hipGetLastError());
+    for (int st = 0; st < 5; ++st) {
+      dgx_status r = enqueue_rhs(h, u, u, nullptr, EPI_RK, CK_A[st], CK_B[st]);
+      if (r != DGX_OK) return r;
+    }
+  }
+  return DGX_OK;
+}
+
+dgx_status dgx_integrals(dgx_handle h, const double* u, const double* du, double* out7) {
+  if (!h) return DGX_EINVAL;
+  CHKDEV(h, u, state_bytes(h), "u");
+  if (du) CHKDEV(h, du, state_bytes(h), "du");
+  CHKDEV(h, out7, sizeof(double) * 7, "out7");
+  HIPCHK(h, h->L->integrals(h->stream, u, du, h->partial, h->g));
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, h->stream, h->partial, h->npart, out7);
+  HIPCHK(h, hipGetLastError());
+  return DGX_OK;
+}
+
+dgx_status dgx_check(dgx_handle h, int32_t* flag) {
+  if (!h || !flag) return DGX_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  int f = 0;
+  HIPCHK(h, hipMemcpy(&f, h->flag, sizeof(int), hipMemcpyDeviceToHost));
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, h->stream, h->flag);
+  HIPCHK(h, hipGetLastError());
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  *flag = f;
+  return f ? DGX_ENONPHYS : DGX_OK;
+}
+
+const char* dgx_last_error(dgx_handle h) { return h ? h->err.c_str() : "invalid handle"; }
+
+dgx_status dgx_profile_enable(dgx_handle h, int32_t on) {
+  if (!h) return DGX_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->prof = on != 0;
+  h->ev_used = 0;
+  h->launches = 0;
+  h->prof_ms = 0.0;
+  return DGX_OK;
+}
+
+dgx_status dgx_profile_read(dgx_handle h, double* avg_ms, int64_t* launches, const char** name) {
+  if (!h) return DGX_EINVAL;
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (size_t i = 0; i + 1 < h->ev_used; i += 2) {
+    float ms = 0.f;
+    HIPCHK(h, hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
+    h->prof_ms += ms;
+    h->launches += 1;
+  }
+  h->ev_used = 0;
+  if (avg_ms) *avg_ms = h->launches ? h->prof_ms / h->launches : 0.0;
+  if (launches) *launches = h->launches;
+  if (name) *name = h->L->volume_name;
+  return DGX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,167 @@
+// physics.h -- pointwise ideal-gas Euler physics for the gfx950 kernels.
+//
+// Conservation law of Eq. (1) (Section 2) for the Euler equations of an ideal gas,
+// no source term.  Two-point and interface fluxes named in Sections 2.3.1 and 3.1:
+// the entropy-conservative, kinetic-energy-preserving volume flux, the central flux,
+// local Lax-Friedrichs and HLL.  Direction is a compile-time parameter so velocity
+// components stay in registers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace dgx {
+
+// Primitive state kept per node: rho, v, p, and beta = rho/p (the argument of the
+// second logarithmic mean, computed once per node instead of once per pair).
+template <typename T>
+struct Prim {
+  T rho, v[3], p, beta;
+};
+
+// Logarithmic mean {{a}}_ln = (b - a)/(ln b - ln a) and its reciprocal.  Near-equal
+// arguments use the series of 2 artanh(z)/z in z^2 = ((b-a)/(b+a))^2 below 1e-4,
+// the threshold of the efficiency reference the paper cites (Section 3.2).
+__device__ __forceinline__ double ln_mean(double a, double b) {
+  const double s = a + b, d = b - a;
+  const double z = d / s, z2 = z * z;
+  if (z2 < 1.0e-4) return s / (2.0 + z2 * (2.0 / 3.0 + z2 * (2.0 / 5.0 + z2 * (2.0 / 7.0))));
+  return d / log(b / a);
+}
+
+__device__ __forceinline__ double inv_ln_mean(double a, double b) {
+  const double s = a + b, d = b - a;
+  const double z = d / s, z2 = z * z;
+  if (z2 < 1.0e-4) return (2.0 + z2 * (2.0 / 3.0 + z2 * (2.0 / 5.0 + z2 * (2.0 / 7.0)))) / s;
+  return log(b / a) / d;
+}
+
+// Mixed precision: the near-equal branch is evaluated in float64, the log branch in
+// float32.
+__device__ __forceinline__ float ln_mean(float a, float b) {
+  const double ad = a, bd = b, s = ad + bd, d = bd - ad;
+  const double z = d / s, z2 = z * z;
+  if (z2 < 1.0e-4)
+    return (float)(s / (2.0 + z2 * (2.0 / 3.0 + z2 * (2.0 / 5.0 + z2 * (2.0 / 7.0)))));
+  return (b - a) / __logf(b / a);
+}
+
+__device__ __forceinline__ float inv_ln_mean(float a, float b) {
+  const double ad = a, bd = b, s = ad + bd, d = bd - ad;
+  const double z = d / s, z2 = z * z;
+  if (z2 < 1.0e-4)
+    return (float)((2.0 + z2 * (2.0 / 3.0 + z2 * (2.0 / 5.0 + z2 * (2.0 / 7.0)))) / s);
+  return __logf(b / a) / (b - a);
+}
+
+// Conserved -> primitive.  Returns false for a non-physical state.
+template <int DIM>
+__device__ __forceinline__ bool cons_to_prim(const double (&u)[DIM + 2], double gamma,
+                                             Prim<double>& q) {
+  q.rho = u[0];
+  const double inv = 1.0 / u[0];
+  double v2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) q.v[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) {
+    q.v[k] = u[1 + k] * inv;
+    v2 += q.v[k] * q.v[k];
+  }
+  q.p = (gamma - 1.0) * (u[DIM + 1] - 0.5 * u[0] * v2);
+  q.beta = q.rho / q.p;
+  return (q.rho > 0.0) && (q.p > 0.0) && (q.p < 1.0e300) && (q.rho < 1.0e300);
+}
+
+// Entropy-conservative, kinetic-energy-preserving two-point flux in direction D:
+//   f_rho  = {{rho}}_ln {{v_D}},  f_rhov = f_rho {{v}} + {{p}} e_D,
+//   f_rhoE = f_rho (1/((gamma-1) {{rho/p}}_ln) + v_L.v_R/2) + (p_L v_DR + p_R v_DL)/2.
+template <int DIM, int D, typename T>
+__device__ __forceinline__ void ec_flux(const Prim<T>& L, const Prim<T>& R, T inv_gm1,
+                                        T (&f)[DIM + 2]) {
+  const T rho_ln = ln_mean(L.rho, R.rho);
+  const T ibeta = inv_ln_mean(L.beta, R.beta);
+  const T half = T(0.5);
+  T vLvR = L.v[0] * R.v[0];
+#pragma unroll
+  for (int k = 1; k < DIM; ++k) vLvR += L.v[k] * R.v[k];
+  const T frho = rho_ln * (half * (L.v[D] + R.v[D]));
+  const T pavg = half * (L.p + R.p);
+  f[0] = frho;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) f[1 + k] = frho * (half * (L.v[k] + R.v[k])) + (k == D ? pavg : T(0));
+  f[DIM + 1] = frho * (ibeta * inv_gm1 + half * vLvR) + half * (L.p * R.v[D] + R.p * L.v[D]);
+}
+
+// Physical flux f^D(u) = (rho v_D, rho v_D v + p e_D, v_D (rho E + p)).
+template <int DIM, int D>
+__device__ __forceinline__ void phys_flux(const double (&u)[DIM + 2], const Prim<double>& q,
+                                          double (&f)[DIM + 2]) {
+  f[0] = u[1 + D];
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) f[1 + k] = u[1 + D] * q.v[k] + (k == D ? q.p : 0.0);
+  f[DIM + 1] = q.v[D] * (u[DIM + 1] + q.p);
+}
+
+// Central flux (f(u_L) + f(u_R))/2 (flux differencing with it is the weak form).
+template <int DIM, int D>
+__device__ __forceinline__ void central_flux(const double (&uL)[DIM + 2], const Prim<double>& L,
+                                             const double (&uR)[DIM + 2], const Prim<double>& R,
+                                             double (&f)[DIM + 2]) {
+  double fL[DIM + 2], fR[DIM + 2];
+  phys_flux<DIM, D>(uL, L, fL);
+  phys_flux<DIM, D>(uR, R, fR);
+#pragma unroll
+  for (int v = 0; v < DIM + 2; ++v) f[v] = 0.5 * (fL[v] + fR[v]);
+}
+
+// Local Lax-Friedrichs: (f_L + f_R)/2 - lambda (u_R - u_L)/2,
+// lambda = max(|v_DL| + c_L, |v_DR| + c_R).
+template <int DIM, int D>
+__device__ __forceinline__ void llf_flux(const double (&uL)[DIM + 2], const Prim<double>& L,
+                                         const double (&uR)[DIM + 2], const Prim<double>& R,
+                                         double gamma, double (&f)[DIM + 2]) {
+  double fL[DIM + 2], fR[DIM + 2];
+  phys_flux<DIM, D>(uL, L, fL);
+  phys_flux<DIM, D>(uR, R, fR);
+  const double cL = sqrt(gamma * L.p / L.rho), cR = sqrt(gamma * R.p / R.rho);
+  const double lam = fmax(fabs(L.v[D]) + cL, fabs(R.v[D]) + cR);
+#pragma unroll
+  for (int v = 0; v < DIM + 2; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
+}
+
+// HLL with s_L = min(v_DL - c_L, v_DR - c_R), s_R = max(v_DL + c_L, v_DR + c_R).
+template <int DIM, int D>
+__device__ __forceinline__ void hll_flux(const double (&uL)[DIM + 2], const Prim<double>& L,
+                                         const double (&uR)[DIM + 2], const Prim<double>& R,
+                                         double gamma, double (&f)[DIM + 2]) {
+  double fL[DIM + 2], fR[DIM + 2];
+  phys_flux<DIM, D>(uL, L, fL);
+  phys_flux<DIM, D>(uR, R, fR);
+  const double cL = sqrt(gamma * L.p / L.rho), cR = sqrt(gamma * R.p / R.rho);
+  const double sL = fmin(L.v[D] - cL, R.v[D] - cR);
+  const double sR = fmax(L.v[D] + cL, R.v[D] + cR);
+  if (sL >= 0.0) {
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v) f[v] = fL[v];
+  } else if (sR <= 0.0) {
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v) f[v] = fR[v];
+  } else {
+    const double inv = 1.0 / (sR - sL);
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v)
+      f[v] = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) * inv;
+  }
+}
+
+enum { SURF_LLF = 0, SURF_HLL = 1, SURF_EC = 2, SURF_NONE = 3 };
+
+template <int DIM, int D, int SURF>
+__device__ __forceinline__ void surface_flux(const double (&uL)[DIM + 2], const Prim<double>& L,
+                                             const double (&uR)[DIM + 2], const Prim<double>& R,
+                                             double gamma, double (&f)[DIM + 2]) {
+  if constexpr (SURF == SURF_LLF) llf_flux<DIM, D>(uL, L, uR, R, gamma, f);
+  else if constexpr (SURF == SURF_HLL) hll_flux<DIM, D>(uL, L, uR, R, gamma, f);
+  else ec_flux<DIM, D, double>(L, R, 1.0 / (gamma - 1.0), f);
+}
+
+}  // namespace dgx

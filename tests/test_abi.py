@@ -1,0 +1,56 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol that
+include/dgx.h declares, and rejects invalid configurations before touching the device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2108_06476_amd import dgx
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dgx.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(dgx_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_binding_exports():
+    assert sorted(dgx.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    L = C.CDLL(dgx.LIB_PATH)
+    missing = [s for s in _declared() if not hasattr(L, s)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("field,value", [("dim", 4), ("polydeg", 0), ("gamma", 1.0),
+                                         ("volume", 9), ("surface", 7), ("precision", 5)])
+def test_invalid_config_rejected_on_host(field, value):
+    L = dgx.lib()
+    cfg = dgx.make_config(3, 3, (2, 2, 2), (0, 0, 0), (1, 1, 1))
+    setattr(cfg, field, value)
+    h = C.c_void_p()
+    st = L.dgx_create(C.byref(cfg), None, C.byref(h))
+    assert st == 1 and not h.value
+
+
+def test_unsupported_config_reported():
+    L = dgx.lib()
+    h = C.c_void_p()
+    cfg = dgx.make_config(3, 9, (2, 2, 2), (0, 0, 0), (1, 1, 1))      # polydeg not compiled
+    assert L.dgx_create(C.byref(cfg), None, C.byref(h)) == 5
+    cfg = dgx.make_config(3, 3, (2, 2, 2), (0, 0, 0), (1, 1, 1), volume="central",
+                          precision="mixed")
+    assert L.dgx_create(C.byref(cfg), None, C.byref(h)) == 5
+
+
+def test_null_handle_calls_fail_cleanly():
+    L = dgx.lib()
+    assert L.dgx_rhs(None, None, None, C.c_double(0.0)) == 1
+    assert L.dgx_destroy(None) == 1
+    assert L.dgx_num_nodes(None) == -1
