@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -111,6 +112,12 @@ __global__ __launch_bounds__(256) void k_sum_final(const double* __restrict__ pa
   if (threadIdx.x < 7) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
+__global__ __launch_bounds__(256) void k_copy(const double* __restrict__ src,
+                                              double* __restrict__ dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
 __global__ void k_zero_int(int* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
@@ -128,13 +135,14 @@ struct dgx_solver {
   const Launchers* L = nullptr;
   Geom g{};
   double* tab = nullptr;
-  double* F = nullptr;
+  double* u2 = nullptr;   // second state buffer of the double-buffered RK stages
   double* k = nullptr;
   double* alpha = nullptr;
   double* alpha_raw = nullptr;
   double* energy = nullptr;
   double* partial = nullptr;
-  int64_t npart = 0;
+  int64_t npart = 0;   // wave-speed partials (one per element)
+  int64_t nblk = 0;    // blocks of the element-tiled kernels (integral partials)
   double* dt = nullptr;
   int* flag = nullptr;
   std::string err;
@@ -192,8 +200,8 @@ dgx_status check_dev(dgx_handle h, const void* p, size_t bytes, const char* name
 
 size_t state_bytes(dgx_handle h) { return sizeof(double) * (size_t)h->NV * h->E * h->NN; }
 
-// Optional event timing of the dominant (volume) kernel.
-hipError_t timed_volume(dgx_handle h, const VolArgs& a, int epi) {
+// Launch one stage kernel, optionally bracketed by timing events (the dominant kernel).
+hipError_t launch_stage(dgx_handle h, const StageArgs& a, int epi) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (h->prof) {
     if (h->ev_used + 2 > h->ev.size()) {
@@ -210,8 +218,7 @@ hipError_t timed_volume(dgx_handle h, const VolArgs& a, int epi) {
     hipError_t r = hipEventRecord(e0, h->stream);
     if (r != hipSuccess) return r;
   }
-  hipError_t r = h->L->volume(h->stream, a, h->g, h->cfg.volume, epi, h->cfg.fv_flux,
-                              h->cfg.precision);
+  hipError_t r = h->L->stage(h->stream, a, h->g, h->cfg.volume, epi, h->cfg.precision);
   if (r != hipSuccess) return r;
   if (h->prof) r = hipEventRecord(e1, h->stream);
   return r;
@@ -224,26 +231,33 @@ dgx_status enqueue_indicator(dgx_handle h, const double* u, double* alpha, doubl
   return DGX_OK;
 }
 
-// R(u) into `out` (RHS) or the RK stage update of u in place.
-dgx_status enqueue_rhs(dgx_handle h, const double* u, double* out, const double* alpha_in,
-                       int epi, double A, double B) {
+StageArgs stage_args(dgx_handle h, const double* uin, const double* alpha) {
+  StageArgs a;
+  a.uin = uin;
+  a.uout = nullptr;
+  a.du = nullptr;
+  a.k = h->k;
+  a.alpha = alpha;
+  a.dt = h->dt;
+  a.speed = nullptr;
+  a.A = 0.0;
+  a.B = 0.0;
+  a.surf = h->cfg.surface;
+  a.fvf = h->cfg.fv_flux;
+  return a;
+}
+
+// du = R(u); alpha_in (shock capturing) may be NULL: then the indicator runs first.
+dgx_status enqueue_rhs(dgx_handle h, const double* u, double* du, const double* alpha_in) {
   const double* alpha = alpha_in;
   if (h->cfg.volume == DGX_VOL_SHOCKCAP_HG && !alpha) {
     dgx_status st = enqueue_indicator(h, u, h->alpha, h->alpha_raw, nullptr);
     if (st != DGX_OK) return st;
     alpha = h->alpha;
   }
-  if (h->cfg.surface != DGX_SURF_NONE) HIPCHK(h, h->L->surface(h->stream, u, h->F, h->g, h->cfg.surface));
-  VolArgs a;
-  a.u = u;
-  a.out = out;
-  a.k = h->k;
-  a.F = h->cfg.surface != DGX_SURF_NONE ? h->F : nullptr;
-  a.alpha = alpha;
-  a.dt = h->dt;
-  a.A = A;
-  a.B = B;
-  HIPCHK(h, timed_volume(h, a, epi));
+  StageArgs a = stage_args(h, u, alpha);
+  a.du = du;
+  HIPCHK(h, launch_stage(h, a, EPI_RHS));
   return DGX_OK;
 }
 
@@ -291,6 +305,10 @@ dgx_status dgx_create(const dgx_config* cfg, void* hip_stream, dgx_handle* out) 
   }
   h->stream = (hipStream_t)hip_stream;
   h->L = L;
+  if ((int64_t)h->NV * h->E * h->NN >= ((int64_t)1 << 31)) {   // kernels index in 32 bits
+    delete h;
+    return DGX_EUNSUPPORTED;
+  }
 
   // operator tables
   std::vector<double> T(TAB_SIZE, 0.0);
@@ -318,7 +336,8 @@ dgx_status dgx_create(const dgx_config* cfg, void* hip_stream, dgx_handle* out) 
   }
 
   const int64_t nblk = (h->E + L->ne - 1) / L->ne;
-  h->npart = nblk;
+  h->npart = h->E;   // wave-speed partials: one per element
+  h->nblk = nblk;
   auto alloc = [&](void** p, size_t bytes) -> bool {
     if (hipMalloc(p, bytes) != hipSuccess) {
       (void)hipGetLastError();
@@ -327,12 +346,12 @@ dgx_status dgx_create(const dgx_config* cfg, void* hip_stream, dgx_handle* out) 
     return true;
   };
   bool ok = alloc((void**)&h->tab, sizeof(double) * TAB_SIZE) &&
-            alloc((void**)&h->F, sizeof(double) * (size_t)h->dim * h->NV * h->E * h->NF) &&
+            alloc((void**)&h->u2, state_bytes(h)) &&
             alloc((void**)&h->k, state_bytes(h)) &&
             alloc((void**)&h->alpha, sizeof(double) * h->E) &&
             alloc((void**)&h->alpha_raw, sizeof(double) * h->E) &&
             alloc((void**)&h->energy, sizeof(double) * h->E) &&
-            alloc((void**)&h->partial, sizeof(double) * 7 * (size_t)nblk) &&
+            alloc((void**)&h->partial, sizeof(double) * std::max<size_t>(7 * (size_t)nblk, (size_t)h->E)) &&
             alloc((void**)&h->dt, sizeof(double) * 2) && alloc((void**)&h->flag, sizeof(int) * 2);
   if (!ok) {
     dgx_destroy(h);
@@ -359,7 +378,7 @@ dgx_status dgx_destroy(dgx_handle h) {
   if (!h) return DGX_EINVAL;
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
-  for (void* p : {(void*)h->tab, (void*)h->F, (void*)h->k, (void*)h->alpha, (void*)h->alpha_raw,
+  for (void* p : {(void*)h->tab, (void*)h->u2, (void*)h->k, (void*)h->alpha, (void*)h->alpha_raw,
                   (void*)h->energy, (void*)h->partial, (void*)h->dt, (void*)h->flag})
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
@@ -389,7 +408,7 @@ dgx_status dgx_rhs(dgx_handle h, const double* u, double* du, double t) {
   CHKDEV(h, u, state_bytes(h), "u");
   CHKDEV(h, du, state_bytes(h), "du");
   if (u == du) return fail(h, DGX_EINVAL, "u and du must not overlap");
-  return enqueue_rhs(h, u, du, nullptr, EPI_RHS, 0.0, 0.0);
+  return enqueue_rhs(h, u, du, nullptr);
 }
 
 dgx_status dgx_rhs_alpha(dgx_handle h, const double* u, const double* alpha, double* du) {
@@ -400,7 +419,7 @@ dgx_status dgx_rhs_alpha(dgx_handle h, const double* u, const double* alpha, dou
   CHKDEV(h, du, state_bytes(h), "du");
   CHKDEV(h, alpha, sizeof(double) * h->E, "alpha");
   if (u == du) return fail(h, DGX_EINVAL, "u and du must not overlap");
-  return enqueue_rhs(h, u, du, alpha, EPI_RHS, 0.0, 0.0);
+  return enqueue_rhs(h, u, du, alpha);
 }
 
 dgx_status dgx_indicator(dgx_handle h, const double* u, double* alpha, double* alpha_raw,
@@ -433,9 +452,16 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
   if (!(cfl > 0.0) && !(dt_fixed > 0.0)) return fail(h, DGX_EINVAL, "need cfl > 0 or dt_fixed > 0");
   CHKDEV(h, u, state_bytes(h), "u");
   if (t) CHKDEV(h, t, sizeof(double), "t");
+  if (nsteps == 0) return DGX_OK;
+  const bool adaptive = cfl > 0.0;
+  // the state alternates between u and the library's u2, stage by stage: a stage reads the
+  // neighbours' face states of its input while other blocks write their output
+  double* buf[2] = {u, h->u2};
+  int cur = 0;
+  if (adaptive) HIPCHK(h, h->L->maxspeed(h->stream, u, h->partial, h->g));
   for (int s = 0; s < nsteps; ++s) {
-    if (cfl > 0.0) {
-      HIPCHK(h, h->L->maxspeed(h->stream, u, h->partial, h->g));
+    if (adaptive) {
+      // partials: from the wave-speed pass (first step) or from the last stage of the step before
       hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, h->stream, h->partial, h->npart, cfl,
                          (double)(h->N + 1), h->dt, t);
     } else {
@@ -443,9 +469,26 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
     }
     HIPCHK(h, hipGetLastError());
     for (int st = 0; st < 5; ++st) {
-      dgx_status r = enqueue_rhs(h, u, u, nullptr, EPI_RK, CK_A[st], CK_B[st]);
-      if (r != DGX_OK) return r;
+      const double* uin = buf[cur];
+      const double* alpha = nullptr;
+      if (h->cfg.volume == DGX_VOL_SHOCKCAP_HG) {
+        dgx_status r = enqueue_indicator(h, uin, h->alpha, h->alpha_raw, nullptr);
+        if (r != DGX_OK) return r;
+        alpha = h->alpha;
+      }
+      StageArgs a = stage_args(h, uin, alpha);
+      a.uout = buf[1 - cur];
+      a.A = CK_A[st];
+      a.B = CK_B[st];
+      a.speed = (adaptive && st == 4 && s + 1 < nsteps) ? h->partial : nullptr;
+      HIPCHK(h, launch_stage(h, a, EPI_RK));
+      cur = 1 - cur;
     }
+  }
+  if (cur != 0) {
+    const int64_t n = (int64_t)h->NV * h->E * h->NN;
+    hipLaunchKernelGGL(k_copy, dim3(2048), dim3(256), 0, h->stream, h->u2, u, n);
+    HIPCHK(h, hipGetLastError());
   }
   return DGX_OK;
 }
@@ -456,7 +499,7 @@ dgx_status dgx_integrals(dgx_handle h, const double* u, const double* du, double
   if (du) CHKDEV(h, du, state_bytes(h), "du");
   CHKDEV(h, out7, sizeof(double) * 7, "out7");
   HIPCHK(h, h->L->integrals(h->stream, u, du, h->partial, h->g));
-  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, h->stream, h->partial, h->npart, out7);
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, h->stream, h->partial, h->nblk, out7);
   HIPCHK(h, hipGetLastError());
   return DGX_OK;
 }

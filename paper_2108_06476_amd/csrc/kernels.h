@@ -62,124 +62,179 @@ __device__ __forceinline__ int64_t neighbour(const Geom& g, int64_t e, int d, in
   return c0 + (int64_t)g.K[0] * (c1 + (int64_t)g.K[1] * c2);
 }
 
+// Element coordinates (32-bit; the library limits nvar * nodes below 2^31) and the periodic
+// face neighbour in a runtime direction d: e + (wrapped c_d +- 1 - c_d) * stride_d.
+__device__ __forceinline__ void elem_xyz(const Geom& g, int e, int (&c)[3]) {
+  const unsigned q = (unsigned)e / (unsigned)g.K[0];
+  c[0] = e - (int)q * g.K[0];
+  const unsigned r = q / (unsigned)g.K[1];
+  c[1] = (int)q - (int)r * g.K[1];
+  c[2] = (int)r;
+}
+
+__device__ __forceinline__ int elem_nb(const Geom& g, int e, const int (&c)[3], int d, int s) {
+  const int Kd = d == 0 ? g.K[0] : (d == 1 ? g.K[1] : g.K[2]);
+  const int cd = d == 0 ? c[0] : (d == 1 ? c[1] : c[2]);
+  const int sd = d == 0 ? 1 : (d == 1 ? g.K[0] : g.K[0] * g.K[1]);
+  int x = cd + s;
+  x = x < 0 ? x + Kd : (x >= Kd ? x - Kd : x);
+  return e + (x - cd) * sd;
+}
+
 template <int n, int D>
 __device__ __forceinline__ int face_index(int node) {
   constexpr int st = Stride<D, n>::value;
   return (node % st) + (node / (st * n)) * st;
 }
 
-// --------------------------------------------------------------------------------------
-// Interface flux: one thread per (direction, element, face node).  F[d][v][e][f] is the
-// numerical flux between the minus neighbour e-d (left) and e (right).
-// --------------------------------------------------------------------------------------
-template <int DIM, int N, int SURF, int D>
-__device__ __forceinline__ void surface_one(const double* __restrict__ u, double* __restrict__ F,
-                                            const Geom& g, int64_t e, int f) {
-  using S = Shape<DIM, N>;
-  constexpr int n = S::n, st = Stride<D, n>::value;
-  const int64_t eL = neighbour(g, e, D, -1);
-  // node with index_D = 0 and face index f, and its partner with index_D = N
-  const int nodeR = (f % st) + (f / st) * st * n;
-  const int nodeL = nodeR + N * st;
-  const int64_t ENN = g.E * S::NN;
-  double uL[DIM + 2], uR[DIM + 2];
-#pragma unroll
-  for (int v = 0; v < DIM + 2; ++v) {
-    uL[v] = u[v * ENN + eL * S::NN + nodeL];
-    uR[v] = u[v * ENN + e * S::NN + nodeR];
-  }
-  Prim<double> L, R;
-  const bool okL = cons_to_prim<DIM>(uL, g.gamma, L);
-  const bool okR = cons_to_prim<DIM>(uR, g.gamma, R);
-  if (!(okL && okR)) *g.flag = 1;
-  double fs[DIM + 2];
-  surface_flux<DIM, D, SURF>(uL, L, uR, R, g.gamma, fs);
-  const int64_t EF = g.E * S::NF;
-#pragma unroll
-  for (int v = 0; v < DIM + 2; ++v) F[((int64_t)D * (DIM + 2) + v) * EF + e * S::NF + f] = fs[v];
+// Orders LDS accesses of one wavefront: the wait retires the wave's outstanding LDS
+// operations and the memory clobber keeps the compiler from moving any memory access
+// across this point (the wave-barrier intrinsic alone does not order memory).
+__device__ __forceinline__ void wave_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
 }
 
-template <int DIM, int N, int SURF>
-__global__ __launch_bounds__(256) void k_surface(const double* __restrict__ u,
-                                                 double* __restrict__ F, Geom g) {
-  using S = Shape<DIM, N>;
-  const int64_t EF = g.E * S::NF;
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= DIM * EF) return;
-  const int d = (int)(gid / EF);
-  const int64_t r = gid - d * EF;
-  const int64_t e = r / S::NF;
-  const int f = (int)(r - e * S::NF);
-  if (d == 0) surface_one<DIM, N, SURF, 0>(u, F, g, e, f);
-  else if (d == 1) surface_one<DIM, N, SURF, 1>(u, F, g, e, f);
-  else if constexpr (DIM == 3) surface_one<DIM, N, SURF, 2>(u, F, g, e, f);
+// An element of exactly one wavefront (64 nodes: N = 3 in 3D, N = 7 in 2D) exchanges data
+// only within its wave: wave-level ordering replaces block barriers.
+template <int DIM, int N>
+struct WaveElem {
+  static constexpr bool value = Shape<DIM, N>::NN == 64;
+};
+
+template <int DIM, int N>
+__device__ __forceinline__ void elem_sync() {
+  if constexpr (WaveElem<DIM, N>::value) wave_sync();
+  else __syncthreads();
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs of the chip, each with its own L2.
+// Give every XCD a contiguous range of element tiles so that face neighbours (x: the next
+// element, y: K_x elements away) are mostly read from the same L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
+  const int64_t per = nb / 8, rem = nb % 8;
+  const int64_t x = b % 8, i = b / 8;
+  return x * per + (x < rem ? x : rem) + i;
+}
+
+template <int DIM, int D>
+__device__ __forceinline__ void face_flux(int surf, const double (&uL)[DIM + 2], const Prim<double>& L,
+                                          const double (&uR)[DIM + 2], const Prim<double>& R,
+                                          double gamma, double (&f)[DIM + 2]) {
+  if (surf == SURF_LLF) llf_flux<DIM, D>(uL, L, uR, R, gamma, f);
+  else if (surf == SURF_HLL) hll_flux<DIM, D>(uL, L, uR, R, gamma, f);
+  else ec_flux<DIM, D, double>(L, R, 1.0 / (gamma - 1.0), f);
 }
 
 // --------------------------------------------------------------------------------------
-// Volume term + surface lift + Jacobian (+ low-storage RK stage), one thread per node,
-// Shape::NE elements per block staged in LDS.
-//
-//   R = sum_d [ -(2/h_d) sum_{m != i_d} S_{i_d m} f#(u, u_m) ]                (DG part)
-//   R = (1 - alpha) R_DG + alpha sum_d [ -(2/h_d) (F_{i+1/2} - F_{i-1/2}) / w_i ]
-//       + (2/h_d)/w_0 F_minus [i_d == 0] - (2/h_d)/w_N F_plus [i_d == N]       (lift)
-// Epilogue: RHS: du = R.  RK: k = A k + dt R; u = u + B k (u read and written by the
-// same thread; the interface fluxes were computed from u beforehand).
+// One stage of the right-hand side, one thread per node, Shape::NE elements per block
+// (element-tiled, staged in LDS):
+//   surface: every element evaluates the numerical flux on its 2*dim faces (the face nodes
+//            are spread over all threads of the block; each interface is evaluated by both
+//            of its elements from the same two states, so both get the same value), and
+//            lifts it to its boundary nodes:  +(2/h_d)/w_0 F* at i_d = 0, -(2/h_d)/w_N F* at i_d = N;
+//   volume:  -(2/h_d) sum_{m != i_d} S_{i_d m} f#(u, u_m), each pair evaluated once;
+//   shock capturing: R_vol = (1 - alpha) R_DG + alpha R_FV (alpha = 0 skips the FV part);
+//   epilogue: RHS: du = R;  RK: k = A k + dt R, u_out = u_in + B k, and optionally the
+//            per-block maximum wave speed of u_out for the next time step.
+// u_in is only read and u_out only written (they must differ in RK mode: neighbours read
+// u_in); k is read and written by the owning thread.
 // --------------------------------------------------------------------------------------
-template <typename RT, int DIM, int NE_NN, bool CONS>
-struct VolLds {
+template <typename RT, int DIM, int NE_NN, int XB, bool CONS>
+struct StageLds {
   RT rho[NE_NN], v[DIM][NE_NN], p[NE_NN], beta[NE_NN];
+  double c[NE_NN];                    // sound speed (face fluxes)
+  alignas(16) unsigned char xb[XB];   // per element: partner contributions | wave speeds
   double u[CONS ? DIM + 2 : 1][CONS ? NE_NN : 1];
 };
 
+// The scratch buffer xb holds one fixed-size slot per element; every view of it (partner
+// contributions [NV][NN], wave speeds [DIM][NN]) stays inside the element's own slot, so
+// elements never touch each other's scratch (with one element per wave, waves run without
+// block barriers).
+template <int DIM, int N, typename RT>
+struct StageShape {
+  using S = Shape<DIM, N>;
+  static constexpr int NENN = S::NE * S::NN;
+  static constexpr int SLOT_X = (int)sizeof(RT) * S::NV * S::NN;
+  static constexpr int SLOT_S = 8 * DIM * S::NN;
+  static constexpr int SLOT0 = SLOT_X > SLOT_S ? SLOT_X : SLOT_S;
+  static constexpr int SLOT = (SLOT0 + 15) / 16 * 16;
+  static constexpr int XB = S::NE * SLOT;
+};
+
+// Unique pairs along direction D.  In round r every node i pairs with i + r (mod n) and
+// evaluates the symmetric two-point flux once: it keeps S_{i,m} f and hands S_{m,i} f to
+// node m through LDS.  Rounds r = 1..(n-1)/2 cover every pair once; for even n the extra
+// round r = n/2 is computed by the nodes i < n/2 only.  All threads of the block pass every
+// barrier; `on` masks threads without an element.
 template <int DIM, int N, int D, int VOL, typename RT, typename L>
-__device__ __forceinline__ void volume_dir(const L& s, int base, int node, const Prim<RT>& me,
+__device__ __forceinline__ void volume_dir(const L& s, RT* __restrict__ x /* element slot */,
+                                           bool on, int base,
+                                           int node, const Prim<RT>& me,
                                            const double (&ume)[DIM + 2], const double* sS,
                                            RT inv_gm1, RT (&acc)[DIM + 2]) {
   constexpr int n = N + 1, st = Stride<D, n>::value;
+  constexpr int NN = Shape<DIM, N>::NN;
+  constexpr int FULL = (n - 1) / 2;
+  constexpr int ROUNDS = FULL + (n % 2 == 0 ? 1 : 0);
   const int id = (node / st) % n;
   const int nb = base + node - id * st;
 #pragma unroll
-  for (int sft = 1; sft <= N; ++sft) {
-    int m = id + sft;
+  for (int r = 1; r <= ROUNDS; ++r) {
+    const bool half = (r > FULL);
+    int m = id + r;
     if (m >= n) m -= n;
     const int pn = nb + m * st;
-    Prim<RT> q;
-    q.rho = s.rho[pn];
+    if (on && (!half || id < n / 2)) {
+      Prim<RT> q;
+      q.rho = s.rho[pn];
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) q.v[k] = s.v[k][pn];
-    q.p = s.p[pn];
-    q.beta = s.beta[pn];
-    RT f[DIM + 2];
-    if constexpr (VOL == VOL_CENTRAL) {
-      double uq[DIM + 2], fd[DIM + 2];
-      Prim<double> qd;
+      for (int k = 0; k < DIM; ++k) q.v[k] = s.v[k][pn];
+      q.p = s.p[pn];
+      q.beta = s.beta[pn];
+      RT f[DIM + 2];
+      if constexpr (VOL == VOL_CENTRAL) {
+        double uq[DIM + 2], fd[DIM + 2];
+        Prim<double> qd, med;
 #pragma unroll
-      for (int v = 0; v < DIM + 2; ++v) uq[v] = s.u[v][pn];
-      qd.rho = q.rho;
+        for (int v = 0; v < DIM + 2; ++v) uq[v] = s.u[v][pn];
+        qd.rho = q.rho;
+        med.rho = me.rho;
 #pragma unroll
-      for (int k = 0; k < 3; ++k) qd.v[k] = k < DIM ? (double)q.v[k] : 0.0;
-      qd.p = q.p;
-      Prim<double> med;
-      med.rho = me.rho;
+        for (int k = 0; k < 3; ++k) {
+          qd.v[k] = k < DIM ? (double)q.v[k] : 0.0;
+          med.v[k] = k < DIM ? (double)me.v[k] : 0.0;
+        }
+        qd.p = q.p;
+        med.p = me.p;
+        central_flux<DIM, D>(ume, med, uq, qd, fd);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) med.v[k] = k < DIM ? (double)me.v[k] : 0.0;
-      med.p = me.p;
-      central_flux<DIM, D>(ume, med, uq, qd, fd);
+        for (int v = 0; v < DIM + 2; ++v) f[v] = (RT)fd[v];
+      } else {
+        ec_flux<DIM, D, RT>(me, q, inv_gm1, f);
+      }
+      const RT cme = (RT)sS[(D * TMAX + id) * TMAX + m];
+      const RT cpa = (RT)sS[(D * TMAX + m) * TMAX + id];
 #pragma unroll
-      for (int v = 0; v < DIM + 2; ++v) f[v] = (RT)fd[v];
-    } else {
-      ec_flux<DIM, D, RT>(me, q, inv_gm1, f);
+      for (int v = 0; v < DIM + 2; ++v) {
+        acc[v] += cme * f[v];
+        x[v * NN + pn - base] = cpa * f[v];
+      }
     }
-    const RT c = (RT)sS[(D * TMAX + id) * TMAX + m];
+    elem_sync<DIM, N>();
+    if (on && (!half || id >= n / 2)) {
 #pragma unroll
-    for (int v = 0; v < DIM + 2; ++v) acc[v] += c * f[v];
+      for (int v = 0; v < DIM + 2; ++v) acc[v] += x[v * NN + node];
+    }
+    elem_sync<DIM, N>();
   }
 }
 
 // First-order FV on the LGL subcells in direction D with the fv flux (LLF or HLL):
 // acc += -(2/h_d)/w_i (F_{i+1/2} - F_{i-1/2}), element-boundary subcell fluxes zero.
-template <int DIM, int N, int D, int FVF, typename L>
-__device__ __forceinline__ void fv_dir(const L& s, int base, int node, const Prim<double>& me,
+template <int DIM, int N, int D, typename L>
+__device__ __forceinline__ void fv_dir(const L& s, int fvf, int base, int node, const Prim<double>& me,
                                        const double (&ume)[DIM + 2], const double* sFV,
                                        double gamma, double (&acc)[DIM + 2]) {
   constexpr int n = N + 1, st = Stride<D, n>::value;
@@ -196,78 +251,116 @@ __device__ __forceinline__ void fv_dir(const L& s, int base, int node, const Pri
     for (int k = 0; k < DIM; ++k) q.v[k] = s.v[k][pn];
     q.p = s.p[pn];
     q.beta = s.beta[pn];
+    q.c = s.c[pn];
   };
   if (id < N) {
     double uq[DIM + 2];
     Prim<double> q;
     load(base + node + st, uq, q);
-    surface_flux<DIM, D, FVF>(ume, me, uq, q, gamma, Fp);
+    face_flux<DIM, D>(fvf, ume, me, uq, q, gamma, Fp);
   }
   if (id > 0) {
     double uq[DIM + 2];
     Prim<double> q;
     load(base + node - st, uq, q);
-    surface_flux<DIM, D, FVF>(uq, q, ume, me, gamma, Fm);
+    face_flux<DIM, D>(fvf, uq, q, ume, me, gamma, Fm);
   }
   const double c = sFV[D * TMAX + id];
 #pragma unroll
   for (int v = 0; v < DIM + 2; ++v) acc[v] += c * (Fp[v] - Fm[v]);
 }
 
+// Surface term of one node in direction D: a node with index_D = 0 (N) lies on the
+// element's minus (plus) face; it evaluates the numerical flux with the neighbour's node
+// across that face and lifts it, +(2/h_D)/w_0 F* (minus) or -(2/h_D)/w_N F* (plus).  Both
+// elements of an interface evaluate it from the same (left, right) states in the same
+// order, so they obtain the same value.
 template <int DIM, int N, int D>
-__device__ __forceinline__ void lift_dir(const double* __restrict__ F, const Geom& g, int64_t e,
-                                         int node, const double* sL, double (&R)[DIM + 2]) {
+__device__ __forceinline__ void surface_dir(const double* __restrict__ u, const Geom& g, int surf,
+                                            int e, const int (&ec)[3], int node,
+                                            const double (&um)[DIM + 2], const Prim<double>& qm,
+                                            const double* sL, double (&R)[DIM + 2]) {
   using S = Shape<DIM, N>;
-  constexpr int n = S::n, st = Stride<D, n>::value;
+  constexpr int n = S::n, NN = S::NN, NV = S::NV, st = Stride<D, n>::value;
   const int id = (node / st) % n;
-  const int64_t EF = g.E * S::NF;
-  const int f = face_index<n, D>(node);
-  if (id == 0) {
-    const double c = sL[D * 2 + 0];
+  if (id != 0 && id != N) return;
+  const bool plus = (id == N);
+  const int oth = plus ? node - N * st : node + N * st;
+  const int enb = elem_nb(g, e, ec, D, plus ? 1 : -1);
+  const unsigned ENN = (unsigned)g.E * NN;
+  double un[NV];
 #pragma unroll
-    for (int v = 0; v < DIM + 2; ++v) R[v] += c * F[((int64_t)D * (DIM + 2) + v) * EF + e * S::NF + f];
-  }
-  if (id == N) {
-    const double c = sL[D * 2 + 1];
-    const int64_t ep = neighbour(g, e, D, +1);
+  for (int v = 0; v < NV; ++v) un[v] = u[v * ENN + (unsigned)enb * NN + oth];
+  Prim<double> qn;
+  if (!cons_to_prim<DIM>(un, g.gamma, qn)) *g.flag = 1;
+  double uL[NV], uR[NV];
+  Prim<double> qL, qR;
 #pragma unroll
-    for (int v = 0; v < DIM + 2; ++v) R[v] += c * F[((int64_t)D * (DIM + 2) + v) * EF + ep * S::NF + f];
+  for (int v = 0; v < NV; ++v) {
+    uL[v] = plus ? um[v] : un[v];
+    uR[v] = plus ? un[v] : um[v];
   }
+  qL.rho = plus ? qm.rho : qn.rho;
+  qR.rho = plus ? qn.rho : qm.rho;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    qL.v[k] = plus ? qm.v[k] : qn.v[k];
+    qR.v[k] = plus ? qn.v[k] : qm.v[k];
+  }
+  qL.p = plus ? qm.p : qn.p;
+  qR.p = plus ? qn.p : qm.p;
+  qL.beta = plus ? qm.beta : qn.beta;
+  qR.beta = plus ? qn.beta : qm.beta;
+  qL.c = plus ? qm.c : qn.c;
+  qR.c = plus ? qn.c : qm.c;
+  double F[NV];
+  face_flux<DIM, D>(surf, uL, qL, uR, qR, g.gamma, F);
+  const double c = plus ? sL[2 * D + 1] : sL[2 * D];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) R[v] += c * F[v];
 }
 
-struct VolArgs {
-  const double* u;       // stage input
-  double* out;           // RHS: du; RK: u (in place)
+struct StageArgs {
+  const double* uin;     // stage input (and the neighbours' face states)
+  double* uout;          // RK: stage output state
+  double* du;            // RHS: right-hand side
   double* k;             // RK register
-  const double* F;       // interface fluxes (nullptr: no surface term)
   const double* alpha;   // blending factors (shock capturing)
   const double* dt;      // device dt (RK)
+  double* speed;         // RK: per-block max wave speed of uout (nullptr: skip)
   double A, B;           // RK stage coefficients
+  int surf;              // SURF_* (SURF_NONE: no surface term)
+  int fvf;               // subcell FV flux (SURF_LLF or SURF_HLL)
 };
 
-template <int DIM, int N, int VOL, int EPI, int FVF, typename RT>
-__global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_volume(VolArgs a, Geom g) {
+template <int DIM, int N, int VOL, int EPI, typename RT>
+__global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_stage(StageArgs a, Geom g) {
   using S = Shape<DIM, N>;
-  constexpr int NV = S::NV, NN = S::NN;
+  using SS = StageShape<DIM, N, RT>;
+  constexpr int NV = S::NV, NN = S::NN, NENN = SS::NENN;
   constexpr bool CONS = (VOL == VOL_CENTRAL || VOL == VOL_SHOCKCAP);
-  __shared__ VolLds<RT, DIM, S::NE * NN, CONS> s;
-  __shared__ double sT[TAB_JAC];
-  for (int i = threadIdx.x; i < TAB_JAC; i += blockDim.x) sT[i] = g.tab[i];
+  __shared__ StageLds<RT, DIM, NENN, SS::XB, CONS> s;
+  __shared__ double sT[TAB_SIZE];
+  for (int i = threadIdx.x; i < TAB_SIZE; i += blockDim.x) sT[i] = g.tab[i];
 
+  const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
   const int le = threadIdx.x / NN;
   const int node = threadIdx.x - le * NN;
-  const int64_t e = (int64_t)blockIdx.x * S::NE + le;
-  const bool active = (le < S::NE) && (e < g.E);
+  const int e = tile * S::NE + le;
+  const bool inb = le < S::NE;
+  const bool active = inb && (e < g.E);
   const int base = le * NN;
-  const int64_t ENN = g.E * NN;
+  const unsigned ENN = (unsigned)g.E * NN;
+  const unsigned own_ix = (unsigned)e * NN + node;
 
   double um[NV];
   Prim<double> qd;
   if (active) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) um[v] = a.u[v * ENN + e * NN + node];
+    for (int v = 0; v < NV; ++v) um[v] = a.uin[v * ENN + own_ix];
     if (!cons_to_prim<DIM>(um, g.gamma, qd)) *g.flag = 1;
     const int li = base + node;
+    s.c[li] = qd.c;
     s.rho[li] = (RT)qd.rho;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) s.v[k][li] = (RT)qd.v[k];
@@ -277,15 +370,30 @@ __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_volume(VolArgs a, 
 #pragma unroll
       for (int v = 0; v < NV; ++v) s.u[v][li] = um[v];
     }
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) um[v] = 1.0;
+    qd.rho = qd.p = qd.beta = qd.c = 1.0;
+    qd.v[0] = qd.v[1] = qd.v[2] = 0.0;
   }
-  __syncthreads();
-  if (!active) return;
 
   double R[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) R[v] = 0.0;
+  __syncthreads();   // tables and staged nodes visible
 
+  // ---- surface: each boundary node's face flux, lifted onto the node
+  if (a.surf != SURF_NONE && active) {
+    int ec[3];
+    elem_xyz(g, e, ec);
+    surface_dir<DIM, N, 0>(a.uin, g, a.surf, e, ec, node, um, qd, sT + TAB_LIFT, R);
+    surface_dir<DIM, N, 1>(a.uin, g, a.surf, e, ec, node, um, qd, sT + TAB_LIFT, R);
+    if constexpr (DIM == 3) surface_dir<DIM, N, 2>(a.uin, g, a.surf, e, ec, node, um, qd, sT + TAB_LIFT, R);
+  }
+
+  // ---- volume
   if constexpr (VOL != VOL_NONE) {
+    RT* x = reinterpret_cast<RT*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);
     Prim<RT> me;
     me.rho = (RT)qd.rho;
 #pragma unroll
@@ -296,47 +404,84 @@ __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_volume(VolArgs a, 
     RT acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = RT(0);
-    volume_dir<DIM, N, 0, VOL, RT>(s, base, node, me, um, sT + TAB_S, inv_gm1, acc);
-    volume_dir<DIM, N, 1, VOL, RT>(s, base, node, me, um, sT + TAB_S, inv_gm1, acc);
-    if constexpr (DIM == 3) volume_dir<DIM, N, 2, VOL, RT>(s, base, node, me, um, sT + TAB_S, inv_gm1, acc);
-    if constexpr (VOL == VOL_SHOCKCAP) {
-      const double al = a.alpha[e];
-      if (al != 0.0) {
-        double fv[NV];
+    volume_dir<DIM, N, 0, VOL, RT>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
+    volume_dir<DIM, N, 1, VOL, RT>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
+    if constexpr (DIM == 3)
+      volume_dir<DIM, N, 2, VOL, RT>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
+    if (active) {
+      if constexpr (VOL == VOL_SHOCKCAP) {
+        const double al = a.alpha[e];
+        if (al != 0.0) {
+          double fv[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) fv[v] = 0.0;
-        fv_dir<DIM, N, 0, FVF>(s, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
-        fv_dir<DIM, N, 1, FVF>(s, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
-        if constexpr (DIM == 3) fv_dir<DIM, N, 2, FVF>(s, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
+          for (int v = 0; v < NV; ++v) fv[v] = 0.0;
+          fv_dir<DIM, N, 0>(s, a.fvf, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
+          fv_dir<DIM, N, 1>(s, a.fvf, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
+          if constexpr (DIM == 3) fv_dir<DIM, N, 2>(s, a.fvf, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) R[v] = (1.0 - al) * (double)acc[v] + al * fv[v];
+          for (int v = 0; v < NV; ++v) R[v] += (1.0 - al) * (double)acc[v] + al * fv[v];
+        } else {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) R[v] += (double)acc[v];
+        }
       } else {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) R[v] = (double)acc[v];
+        for (int v = 0; v < NV; ++v) R[v] += (double)acc[v];
       }
-    } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) R[v] = (double)acc[v];
     }
   }
 
-  if (a.F != nullptr) {
-    lift_dir<DIM, N, 0>(a.F, g, e, node, sT + TAB_LIFT, R);
-    lift_dir<DIM, N, 1>(a.F, g, e, node, sT + TAB_LIFT, R);
-    if constexpr (DIM == 3) lift_dir<DIM, N, 2>(a.F, g, e, node, sT + TAB_LIFT, R);
-  }
-
+  // ---- epilogue
   if constexpr (EPI == EPI_RHS) {
+    if (active) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) a.out[v * ENN + e * NN + node] = R[v];
+      for (int v = 0; v < NV; ++v) a.du[v * ENN + own_ix] = R[v];
+    }
   } else {
-    const double dt = *a.dt;
+    double un[NV];
+    if (active) {
+      const double dt = *a.dt;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const int64_t ix = v * ENN + e * NN + node;
-      const double kv = (a.A == 0.0) ? dt * R[v] : a.A * a.k[ix] + dt * R[v];
-      a.k[ix] = kv;
-      a.out[ix] = um[v] + a.B * kv;
+      for (int v = 0; v < NV; ++v) {
+        const unsigned ix = v * ENN + own_ix;
+        const double kv = (a.A == 0.0) ? dt * R[v] : a.A * a.k[ix] + dt * R[v];
+        a.k[ix] = kv;
+        un[v] = um[v] + a.B * kv;
+        a.uout[ix] = un[v];
+      }
+    }
+    if (a.speed != nullptr) {
+      // per element: sum_d (2/h_d) max over its nodes of |v_d| + c of the new state, one
+      // partial of the next CFL time step per element
+      constexpr int P2 = NN <= 4 ? 4 : NN <= 16 ? 16 : NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
+      double* sp = reinterpret_cast<double*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);   // [DIM][NN]
+      elem_sync<DIM, N>();
+      if (inb) {
+        if (active) {
+          Prim<double> q;
+          if (!cons_to_prim<DIM>(un, g.gamma, q)) *g.flag = 1;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) sp[d * NN + node] = fabs(q.v[d]) + q.c;
+        } else {
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) sp[d * NN + node] = 0.0;
+        }
+      }
+      elem_sync<DIM, N>();
+      for (int h = P2 / 2; h > 0; h >>= 1) {
+        if (inb && node < h && node + h < NN) {
+#pragma unroll
+          for (int d = 0; d < DIM; ++d)
+            sp[d * NN + node] = fmax(sp[d * NN + node], sp[d * NN + node + h]);
+        }
+        elem_sync<DIM, N>();
+      }
+      if (active && node == 0) {
+        double lam = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) lam += sT[TAB_JAC + d] * sp[d * NN];
+        a.speed[e] = lam;
+      }
     }
   }
 }
@@ -440,41 +585,47 @@ __global__ __launch_bounds__(256) void k_smooth(const double* __restrict__ ar,
 // --------------------------------------------------------------------------------------
 template <int DIM, int N>
 __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_maxspeed(const double* __restrict__ u,
-                                                                     double* __restrict__ partial,
-                                                                     Geom g) {
+                                                                       double* __restrict__ partial,
+                                                                       Geom g) {
   using S = Shape<DIM, N>;
   constexpr int NN = S::NN;
+  constexpr int P2 = NN <= 4 ? 4 : NN <= 16 ? 16 : NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
   __shared__ double sm[DIM][S::NE * NN];
   const int le = threadIdx.x / NN;
   const int node = threadIdx.x - le * NN;
   const int64_t e = (int64_t)blockIdx.x * S::NE + le;
-  const bool active = (le < S::NE) && (e < g.E);
+  const bool inb = le < S::NE;
+  const bool active = inb && (e < g.E);
   const int base = le * NN;
   const int64_t ENN = g.E * NN;
-  if (active) {
-    double um[S::NV];
+  if (inb) {
+    if (active) {
+      double um[S::NV];
 #pragma unroll
-    for (int v = 0; v < S::NV; ++v) um[v] = u[v * ENN + e * NN + node];
-    Prim<double> q;
-    if (!cons_to_prim<DIM>(um, g.gamma, q)) *g.flag = 1;
-    const double c = sqrt(g.gamma * q.p / q.rho);
+      for (int v = 0; v < S::NV; ++v) um[v] = u[v * ENN + e * NN + node];
+      Prim<double> q;
+      if (!cons_to_prim<DIM>(um, g.gamma, q)) *g.flag = 1;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) sm[d][base + node] = fabs(q.v[d]) + c;
+      for (int d = 0; d < DIM; ++d) sm[d][base + node] = fabs(q.v[d]) + q.c;
+    } else {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) sm[d][base + node] = 0.0;
+    }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    double best = 0.0;
-    for (int l = 0; l < S::NE; ++l) {
-      if ((int64_t)blockIdx.x * S::NE + l >= g.E) break;
-      double lam = 0.0;
-      for (int d = 0; d < DIM; ++d) {
-        double mx = 0.0;
-        for (int nd = 0; nd < NN; ++nd) mx = fmax(mx, sm[d][l * NN + nd]);
-        lam += g.tab[TAB_JAC + d] * mx;
-      }
-      best = fmax(best, lam);
+  for (int half = P2 / 2; half > 0; half >>= 1) {
+    if (inb && node < half && node + half < NN) {
+#pragma unroll
+      for (int d = 0; d < DIM; ++d)
+        sm[d][base + node] = fmax(sm[d][base + node], sm[d][base + node + half]);
     }
-    partial[blockIdx.x] = best;
+    __syncthreads();
+  }
+  if (active && node == 0) {
+    double lam = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) lam += g.tab[TAB_JAC + d] * sm[d][base];
+    partial[e] = lam;
   }
 }
 

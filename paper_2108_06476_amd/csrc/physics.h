@@ -10,45 +10,62 @@
 
 namespace dgx {
 
-// Primitive state kept per node: rho, v, p, and beta = rho/p (the argument of the
-// second logarithmic mean, computed once per node instead of once per pair).
+// Primitive state kept per node: rho, v, p, beta = rho/p (the argument of the second
+// logarithmic mean, computed once per node instead of once per pair) and the sound speed c.
 template <typename T>
 struct Prim {
-  T rho, v[3], p, beta;
+  T rho, v[3], p, beta, c;
 };
 
-// Logarithmic mean {{a}}_ln = (b - a)/(ln b - ln a) and its reciprocal.  Near-equal
-// arguments use the series of 2 artanh(z)/z in z^2 = ((b-a)/(b+a))^2 below 1e-4,
-// the threshold of the efficiency reference the paper cites (Section 3.2).
+// 1/x from the hardware reciprocal refined by two Newton steps (x > 0, normal).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Logarithmic mean {{a}}_ln = (b - a)/(ln b - ln a) and its reciprocal.  With
+// z = (b - a)/(b + a), ln(b/a) = 2 artanh z, so {{a}}_ln = (a + b)/2 * z/artanh(z) and
+// 1/{{a}}_ln = 2/(a + b) * artanh(z)/z.  Below z^2 = 1e-4 (the threshold of the efficiency
+// reference the paper cites, Section 3.2) both use their Taylor series in z^2 to z^6
+// (truncation below 1.2e-17), so one reciprocal of a + b serves the whole evaluation.
 __device__ __forceinline__ double ln_mean(double a, double b) {
   const double s = a + b, d = b - a;
-  const double z = d / s, z2 = z * z;
-  if (z2 < 1.0e-4) return s / (2.0 + z2 * (2.0 / 3.0 + z2 * (2.0 / 5.0 + z2 * (2.0 / 7.0))));
+  const double r = rcp_nr(s);
+  const double z = d * r, z2 = z * z;
+  if (z2 < 1.0e-4)
+    return 0.5 * s * (1.0 + z2 * (-1.0 / 3.0 + z2 * (-4.0 / 45.0 + z2 * (-44.0 / 945.0))));
   return d / log(b / a);
 }
 
 __device__ __forceinline__ double inv_ln_mean(double a, double b) {
   const double s = a + b, d = b - a;
-  const double z = d / s, z2 = z * z;
-  if (z2 < 1.0e-4) return (2.0 + z2 * (2.0 / 3.0 + z2 * (2.0 / 5.0 + z2 * (2.0 / 7.0)))) / s;
+  const double r = rcp_nr(s);
+  const double z = d * r, z2 = z * z;
+  if (z2 < 1.0e-4)
+    return 2.0 * r * (1.0 + z2 * (1.0 / 3.0 + z2 * (1.0 / 5.0 + z2 * (1.0 / 7.0))));
   return log(b / a) / d;
 }
 
 // Mixed precision: the near-equal branch is evaluated in float64, the log branch in
 // float32.
 __device__ __forceinline__ float ln_mean(float a, float b) {
-  const double ad = a, bd = b, s = ad + bd, d = bd - ad;
-  const double z = d / s, z2 = z * z;
+  const double s = (double)a + (double)b, d = (double)b - (double)a;
+  const double r = rcp_nr(s);
+  const double z = d * r, z2 = z * z;
   if (z2 < 1.0e-4)
-    return (float)(s / (2.0 + z2 * (2.0 / 3.0 + z2 * (2.0 / 5.0 + z2 * (2.0 / 7.0)))));
+    return (float)(0.5 * s * (1.0 + z2 * (-1.0 / 3.0 + z2 * (-4.0 / 45.0 + z2 * (-44.0 / 945.0)))));
   return (b - a) / __logf(b / a);
 }
 
 __device__ __forceinline__ float inv_ln_mean(float a, float b) {
-  const double ad = a, bd = b, s = ad + bd, d = bd - ad;
-  const double z = d / s, z2 = z * z;
+  const double s = (double)a + (double)b, d = (double)b - (double)a;
+  const double r = rcp_nr(s);
+  const double z = d * r, z2 = z * z;
   if (z2 < 1.0e-4)
-    return (float)((2.0 + z2 * (2.0 / 3.0 + z2 * (2.0 / 5.0 + z2 * (2.0 / 7.0)))) / s);
+    return (float)(2.0 * r * (1.0 + z2 * (1.0 / 3.0 + z2 * (1.0 / 5.0 + z2 * (1.0 / 7.0)))));
   return __logf(b / a) / (b - a);
 }
 
@@ -57,7 +74,7 @@ template <int DIM>
 __device__ __forceinline__ bool cons_to_prim(const double (&u)[DIM + 2], double gamma,
                                              Prim<double>& q) {
   q.rho = u[0];
-  const double inv = 1.0 / u[0];
+  const double inv = rcp_nr(u[0]);
   double v2 = 0.0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) q.v[k] = 0.0;
@@ -67,7 +84,8 @@ __device__ __forceinline__ bool cons_to_prim(const double (&u)[DIM + 2], double 
     v2 += q.v[k] * q.v[k];
   }
   q.p = (gamma - 1.0) * (u[DIM + 1] - 0.5 * u[0] * v2);
-  q.beta = q.rho / q.p;
+  q.beta = q.rho * rcp_nr(q.p);
+  q.c = sqrt(gamma * q.p * inv);
   return (q.rho > 0.0) && (q.p > 0.0) && (q.p < 1.0e300) && (q.rho < 1.0e300);
 }
 
@@ -122,8 +140,7 @@ __device__ __forceinline__ void llf_flux(const double (&uL)[DIM + 2], const Prim
   double fL[DIM + 2], fR[DIM + 2];
   phys_flux<DIM, D>(uL, L, fL);
   phys_flux<DIM, D>(uR, R, fR);
-  const double cL = sqrt(gamma * L.p / L.rho), cR = sqrt(gamma * R.p / R.rho);
-  const double lam = fmax(fabs(L.v[D]) + cL, fabs(R.v[D]) + cR);
+  const double lam = fmax(fabs(L.v[D]) + L.c, fabs(R.v[D]) + R.c);
 #pragma unroll
   for (int v = 0; v < DIM + 2; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
 }
@@ -136,9 +153,8 @@ __device__ __forceinline__ void hll_flux(const double (&uL)[DIM + 2], const Prim
   double fL[DIM + 2], fR[DIM + 2];
   phys_flux<DIM, D>(uL, L, fL);
   phys_flux<DIM, D>(uR, R, fR);
-  const double cL = sqrt(gamma * L.p / L.rho), cR = sqrt(gamma * R.p / R.rho);
-  const double sL = fmin(L.v[D] - cL, R.v[D] - cR);
-  const double sR = fmax(L.v[D] + cL, R.v[D] + cR);
+  const double sL = fmin(L.v[D] - L.c, R.v[D] - R.c);
+  const double sR = fmax(L.v[D] + L.c, R.v[D] + R.c);
   if (sL >= 0.0) {
 #pragma unroll
     for (int v = 0; v < DIM + 2; ++v) f[v] = fL[v];
@@ -162,6 +178,62 @@ __device__ __forceinline__ void surface_flux(const double (&uL)[DIM + 2], const 
   if constexpr (SURF == SURF_LLF) llf_flux<DIM, D>(uL, L, uR, R, gamma, f);
   else if constexpr (SURF == SURF_HLL) hll_flux<DIM, D>(uL, L, uR, R, gamma, f);
   else ec_flux<DIM, D, double>(L, R, 1.0 / (gamma - 1.0), f);
+}
+
+// ---- runtime normal direction d (one code path for every face of an element) -------
+
+template <int DIM>
+__device__ __forceinline__ double pick(const double (&a)[3], int d) {
+  return DIM == 3 ? (d == 0 ? a[0] : (d == 1 ? a[1] : a[2])) : (d == 0 ? a[0] : a[1]);
+}
+
+template <int DIM>
+__device__ __forceinline__ void phys_flux_rt(const double (&u)[DIM + 2], const Prim<double>& q,
+                                             int d, double vn, double (&f)[DIM + 2]) {
+  const double mn = DIM == 3 ? (d == 0 ? u[1] : (d == 1 ? u[2] : u[3])) : (d == 0 ? u[1] : u[2]);
+  f[0] = mn;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) f[1 + k] = mn * q.v[k] + (k == d ? q.p : 0.0);
+  f[DIM + 1] = vn * (u[DIM + 1] + q.p);
+}
+
+template <int DIM>
+__device__ __forceinline__ void surface_flux_rt(int surf, int d, const double (&uL)[DIM + 2],
+                                                const Prim<double>& L, const double (&uR)[DIM + 2],
+                                                const Prim<double>& R, double gamma,
+                                                double (&f)[DIM + 2]) {
+  const double vL = pick<DIM>(L.v, d), vR = pick<DIM>(R.v, d);
+  if (surf == SURF_EC) {
+    const double rho_ln = ln_mean(L.rho, R.rho);
+    const double ibeta = inv_ln_mean(L.beta, R.beta);
+    double vLvR = L.v[0] * R.v[0];
+#pragma unroll
+    for (int k = 1; k < DIM; ++k) vLvR += L.v[k] * R.v[k];
+    const double frho = rho_ln * (0.5 * (vL + vR));
+    const double pavg = 0.5 * (L.p + R.p);
+    f[0] = frho;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) f[1 + k] = frho * (0.5 * (L.v[k] + R.v[k])) + (k == d ? pavg : 0.0);
+    f[DIM + 1] = frho * (ibeta * (1.0 / (gamma - 1.0)) + 0.5 * vLvR) + 0.5 * (L.p * vR + R.p * vL);
+    return;
+  }
+  double fL[DIM + 2], fR[DIM + 2];
+  phys_flux_rt<DIM>(uL, L, d, vL, fL);
+  phys_flux_rt<DIM>(uR, R, d, vR, fR);
+  if (surf == SURF_LLF) {
+    const double lam = fmax(fabs(vL) + L.c, fabs(vR) + R.c);
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
+    return;
+  }
+  const double sL = fmin(vL - L.c, vR - R.c);
+  const double sR = fmax(vL + L.c, vR + R.c);
+  const double inv = rcp_nr(sR - sL);
+#pragma unroll
+  for (int v = 0; v < DIM + 2; ++v) {
+    const double mid = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) * inv;
+    f[v] = sL >= 0.0 ? fL[v] : (sR <= 0.0 ? fR[v] : mid);
+  }
 }
 
 }  // namespace dgx

@@ -11,10 +11,8 @@ enum { PREC_FP64 = 0, PREC_MIXED = 1 };
 struct Launchers {
   int threads = 0;   // block size of the element-tiled kernels
   int ne = 0;        // elements per block
-  hipError_t (*surface)(hipStream_t, const double* u, double* F, const Geom&, int surf) = nullptr;
   // returns hipErrorInvalidValue for an unsupported combination
-  hipError_t (*volume)(hipStream_t, const VolArgs&, const Geom&, int vol, int epi, int fvf,
-                       int prec) = nullptr;
+  hipError_t (*stage)(hipStream_t, const StageArgs&, const Geom&, int vol, int epi, int prec) = nullptr;
   hipError_t (*indicator)(hipStream_t, const double* u, double* ar, double* en, const Geom&,
                           double amin, double amax) = nullptr;
   hipError_t (*smooth)(hipStream_t, const double* ar, double* a, const Geom&, int smooth) = nullptr;
@@ -39,46 +37,30 @@ struct Launch {
   using S = Shape<DIM, N>;
   static unsigned blocks(int64_t E) { return (unsigned)((E + S::NE - 1) / S::NE); }
 
-  static hipError_t surface(hipStream_t st, const double* u, double* F, const Geom& g, int surf) {
-    const int64_t tot = (int64_t)DIM * g.E * S::NF;
-    const unsigned nb = (unsigned)((tot + 255) / 256);
-    switch (surf) {
-      case SURF_LLF: hipLaunchKernelGGL((k_surface<DIM, N, SURF_LLF>), dim3(nb), dim3(256), 0, st, u, F, g); break;
-      case SURF_HLL: hipLaunchKernelGGL((k_surface<DIM, N, SURF_HLL>), dim3(nb), dim3(256), 0, st, u, F, g); break;
-      case SURF_EC: hipLaunchKernelGGL((k_surface<DIM, N, SURF_EC>), dim3(nb), dim3(256), 0, st, u, F, g); break;
-      default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-  }
-
-  template <int VOL, int EPI, int FVF, typename RT>
-  static hipError_t vol1(hipStream_t st, const VolArgs& a, const Geom& g) {
-    hipLaunchKernelGGL((k_volume<DIM, N, VOL, EPI, FVF, RT>), dim3(blocks(g.E)), dim3(S::THREADS),
-                       0, st, a, g);
+  template <int VOL, int EPI, typename RT>
+  static hipError_t stage1(hipStream_t st, const StageArgs& a, const Geom& g) {
+    hipLaunchKernelGGL((k_stage<DIM, N, VOL, EPI, RT>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st,
+                       a, g);
     return hipGetLastError();
   }
 
   template <int EPI>
-  static hipError_t vol_epi(hipStream_t st, const VolArgs& a, const Geom& g, int vol, int fvf,
-                            int prec) {
+  static hipError_t stage_epi(hipStream_t st, const StageArgs& a, const Geom& g, int vol, int prec) {
     if (vol == VOL_EC) {
-      if (prec == PREC_MIXED) return vol1<VOL_EC, EPI, SURF_LLF, float>(st, a, g);
-      return vol1<VOL_EC, EPI, SURF_LLF, double>(st, a, g);
+      if (prec == PREC_MIXED) return stage1<VOL_EC, EPI, float>(st, a, g);
+      return stage1<VOL_EC, EPI, double>(st, a, g);
     }
     if (prec != PREC_FP64) return hipErrorInvalidValue;
-    if (vol == VOL_CENTRAL) return vol1<VOL_CENTRAL, EPI, SURF_LLF, double>(st, a, g);
-    if (vol == VOL_NONE) return vol1<VOL_NONE, EPI, SURF_LLF, double>(st, a, g);
-    if (vol == VOL_SHOCKCAP) {
-      if (fvf == SURF_HLL) return vol1<VOL_SHOCKCAP, EPI, SURF_HLL, double>(st, a, g);
-      return vol1<VOL_SHOCKCAP, EPI, SURF_LLF, double>(st, a, g);
-    }
+    if (vol == VOL_CENTRAL) return stage1<VOL_CENTRAL, EPI, double>(st, a, g);
+    if (vol == VOL_NONE) return stage1<VOL_NONE, EPI, double>(st, a, g);
+    if (vol == VOL_SHOCKCAP) return stage1<VOL_SHOCKCAP, EPI, double>(st, a, g);
     return hipErrorInvalidValue;
   }
 
-  static hipError_t volume(hipStream_t st, const VolArgs& a, const Geom& g, int vol, int epi,
-                           int fvf, int prec) {
-    if (epi == EPI_RK) return vol_epi<EPI_RK>(st, a, g, vol, fvf, prec);
-    return vol_epi<EPI_RHS>(st, a, g, vol, fvf, prec);
+  static hipError_t stage(hipStream_t st, const StageArgs& a, const Geom& g, int vol, int epi,
+                          int prec) {
+    if (epi == EPI_RK) return stage_epi<EPI_RK>(st, a, g, vol, prec);
+    return stage_epi<EPI_RHS>(st, a, g, vol, prec);
   }
 
   static hipError_t indicator(hipStream_t st, const double* u, double* ar, double* en,
@@ -118,14 +100,13 @@ struct Launch {
     Launchers L;
     L.threads = S::THREADS;
     L.ne = S::NE;
-    L.surface = &surface;
-    L.volume = &volume;
+    L.stage = &stage;
     L.indicator = &indicator;
     L.smooth = &smooth;
     L.maxspeed = &maxspeed;
     L.integrals = &integrals;
     L.coords = &coords;
-    L.volume_name = "k_volume";
+    L.volume_name = "k_stage";
     return L;
   }
 };
