@@ -34,10 +34,10 @@ def make_state(solver, name):
     import torch
 
     from paper_2108_06476_amd import inputs
-    xyz = solver.node_coords().cpu().numpy()
     if name.startswith("tgv"):
-        u = inputs.tgv(xyz)
-    elif name.startswith("sedov"):
+        return inputs.tgv(solver.node_coords()).contiguous()   # evaluated on the GPU
+    xyz = solver.node_coords().cpu().numpy()
+    if name.startswith("sedov"):
         u = inputs.sedov(xyz)
     else:
         u = inputs.density_wave(xyz)
@@ -107,8 +107,9 @@ def main():
     ap.add_argument("--workload", default="tgv_32")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="rhs,mixed,batched",
-                    help="comma list of extra variants: rhs, mixed, batched ('' for none)")
+    ap.add_argument("--variants", default="rhs,mixed,batched,sedov,dwave",
+                    help="comma list of extra variants: rhs, mixed, batched, sedov, dwave "
+                         "('' for none)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -135,8 +136,10 @@ def main():
     alg_bytes = 160.0 * nodes
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": kname, "avg_ms": avg_ms, "launches": launches}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": stored_traffic("k_stage_tgv32_fp64"),
+                "kernel": kname, "avg_ms": avg_ms, "launches": launches,
+                "alg_bytes_per_launch": alg_bytes}
     _log(f"step: {secs / args.steps * 1e3:.3f} ms/step, {value:.4e} DOF-RHS/s; "
          f"{kname} avg {avg_ms * 1e3:.1f} us")
 
@@ -175,10 +178,21 @@ def main():
         except Exception as e:
             variants["mixed"] = {"error": str(e)}
     if "batched" in want:
+        for prec in ("fp64", "mixed"):
+            try:
+                variants[f"batched_{prec}"] = bench_batched(args, prec)
+            except Exception as e:
+                variants[f"batched_{prec}"] = {"error": str(e)}
+    if "sedov" in want:
         try:
-            variants["batched_fp64"] = bench_batched(args)
+            variants["shockcap_sedov_32_fp64"] = bench_sedov(args)
         except Exception as e:
-            variants["batched_fp64"] = {"error": str(e)}
+            variants["shockcap_sedov_32_fp64"] = {"error": str(e)}
+    if "dwave" in want:
+        try:
+            variants["density_wave_2d_fp64"] = bench_density_wave(args)
+        except Exception as e:
+            variants["density_wave_2d_fp64"] = {"error": str(e)}
     out["variants"] = variants
 
     if not args.no_cpu_baseline:
@@ -186,44 +200,84 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def bench_batched(args):
-    """256 independent TGV runs (K in {8,12,16,24}^3, N in {3,4,5}) advanced together."""
-    import ctypes as C
-
+def bench_batched(args, precision="fp64"):
+    """256 independent TGV runs (K in {8,12,16,24}^3, N in {3,4,5}) advanced together: one
+    launch per RK stage over all runs, steps replayed from a hipGraph, tile shape autotuned."""
     import torch
 
     from paper_2108_06476_amd import dgx, inputs
     runs = inputs.ensemble(256, seed=2109)
-    cfgs = (dgx.Config * len(runs))(*[dgx.make_config(**inputs.ensemble_config(r)) for r in runs])
-    L = dgx.lib()
-    b = C.c_void_p()
-    st = L.dgx_batch_create(cfgs, len(runs), C.c_void_p(torch.cuda.current_stream().cuda_stream),
-                            C.byref(b))
-    if st != 0:
-        raise RuntimeError(f"dgx_batch_create failed: {st}")
-    try:
-        us, total = [], 0
-        for r in runs:
-            c = inputs.ensemble_config(r)
-            o = dgx.Solver(**c)
-            xyz = o.node_coords().cpu().numpy()
-            us.append(torch.from_numpy(inputs.ensemble_state(r, xyz)).cuda())
-            total += o.num_nodes
-            o.close()
-        ptrs = (C.c_void_p * len(us))(*[C.c_void_p(t.data_ptr()) for t in us])
-        steps = max(3, args.steps // 40)
-        st = L.dgx_batch_step(b, ptrs, 1, C.c_double(0.5), None)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st |= L.dgx_batch_step(b, ptrs, steps, C.c_double(0.5), None)
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
-        if st != 0:
-            raise RuntimeError(L.dgx_batch_last_error(b).decode())
-        return {"value": steps * 5 * total / secs, "unit": "DOF-RHS/s", "runs": len(runs),
-                "dof_per_var": total, "steps": steps}
-    finally:
-        L.dgx_batch_destroy(b)
+    cfgs = [dict(inputs.ensemble_config(r), precision=precision) for r in runs]
+    b = dgx.Batch(cfgs)
+    us, total = [], 0
+    for r, c in zip(runs, cfgs):
+        o = dgx.Solver(**dict(c, precision="fp64"))
+        us.append(inputs.ensemble_state(r, o.node_coords()).contiguous())   # on the GPU
+        total += o.num_nodes
+        o.close()
+    t0 = time.perf_counter()
+    shape = b.tune(us, budget_ms=3000)
+    tune_s = time.perf_counter() - t0
+    b.step(us, 2, cfl=0.5)
+    torch.cuda.synchronize()
+    steps = max(4, (args.steps // 20) // 2 * 2)
+    t0 = time.perf_counter()
+    b.step(us, steps, cfl=0.5)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    if b.check():
+        raise RuntimeError("non-physical state in the ensemble")
+    b.close()
+    return {"value": steps * 5 * total / secs, "unit": "DOF-RHS/s", "runs": len(runs),
+            "dof_per_var": total, "steps": steps, "precision": precision,
+            "tile_threads": shape[0], "grid_blocks": shape[1], "tune_s": round(tune_s, 2)}
+
+
+def bench_sedov(args):
+    """Shock capturing: Sedov blast 32^3, N = 3, HG indicator + blended FV, full RK steps."""
+    from paper_2108_06476_amd import dgx, inputs
+    s = dgx.Solver(**inputs.workload("sedov_32"))
+    u = make_state(s, "sedov_32")
+    steps = max(5, args.steps // 10)
+    secs, _ = time_steps(s, u, steps, 2)
+    return {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps}
+
+
+def bench_density_wave(args):
+    """2D density wave 16^2, N = 3: 100 RK steps (launch-bound at this size)."""
+    import torch
+
+    from paper_2108_06476_amd import dgx, inputs
+    s = dgx.Solver(**inputs.workload("density_wave_2d"))
+    u = make_state(s, "density_wave_2d")
+    secs, _ = time_steps(s, u, 100, 5)
+    del torch
+    return {"value": 100 * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": 100,
+            "ms_per_step": secs / 100 * 1e3}
+
+
+def kernel_source_hash():
+    """Hash of the HIP sources; a stored counter measurement applies only to this build."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2108_06476_amd", "csrc", "*"))):
+        if f.endswith((".h", ".hip", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def stored_traffic(name):
+    """HBM bytes per launch of `name` from the committed counter summary, or None when the
+    kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{name}_pmc.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 if __name__ == "__main__":

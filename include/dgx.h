@@ -151,23 +151,32 @@ dgx_status dgx_profile_read(dgx_handle h, double *avg_ms, int64_t *launches, con
 /* ----- ensembles: many independent solvers advanced together ----- */
 typedef struct dgx_batch_s *dgx_batch;
 
-/* nruns configurations (host array, copied); every run is 3D, DGX_VOL_EC,
- * DGX_SURF_LLF or HLL, with its own grid and polydeg; all share one precision. */
+/* nruns configurations (host array, copied); every run is 3D, DGX_VOL_EC, DGX_SURF_LLF or
+ * HLL, polydeg 3..5, with its own grid, extent and gamma; all share one precision.  Each
+ * RK stage of all runs is one persistent launch over (run, element tile) work items, runs
+ * of higher polydeg first; a step (per-run dt + 5 stages) is replayed from a captured
+ * hipGraph.  The library owns each run's second state buffer and RK register. */
 dgx_status dgx_batch_create(const dgx_config *cfgs, int32_t nruns, void *hip_stream,
                             dgx_batch *out);
 dgx_status dgx_batch_destroy(dgx_batch b);
 /* number of nodes of run r (per variable) */
 int64_t dgx_batch_num_nodes(dgx_batch b, int32_t r);
-/* Advance every run by nsteps, each with its own dt from its own state (cfl > 0).
- * u: host array of nruns device pointers, each [5][E_r][n_r^3].  t: device [nruns]
- * (may be NULL). */
+/* Advance every run in place by nsteps CK(5,4) steps, each with its own CFL dt from its
+ * own state (cfl > 0).  u: host array of nruns device pointers, each [5][E_r][n_r^3]
+ * (the dgx_step layout).  t: device [nruns] (may be NULL), advanced by each run's dt. */
 dgx_status dgx_batch_step(dgx_batch b, double *const *u, int32_t nsteps, double cfl,
                           double *t);
 /* du_r = R_r(u_r) for every run (host arrays of device pointers). */
 dgx_status dgx_batch_rhs(dgx_batch b, const double *const *u, double *const *du);
-/* Pick the work-item tile shape by timing the candidates on the current states.
- * budget_ms bounds the tuning time; the choice is kept in the batch. */
+/* Autotuner: time one right-hand side of every run (written into the library's RK
+ * registers; the states u are only read) for each candidate tile shape (threads per block:
+ * 256 or 512, i.e. elements per work item) and persistent grid (2, 4, 8, 16 blocks per CU,
+ * or one block per work item) and keep the fastest.  budget_ms bounds the tuning time. */
 dgx_status dgx_batch_tune(dgx_batch b, double *const *u, int32_t budget_ms);
+/* The current tile shape: threads per block and persistent blocks. */
+dgx_status dgx_batch_shape(dgx_batch b, int32_t *block, int32_t *grid);
+/* Synchronise and report (and clear) the non-physical-state flag of any run. */
+dgx_status dgx_batch_check(dgx_batch b, int32_t *flag);
 const char *dgx_batch_last_error(dgx_batch b);
 
 #ifdef __cplusplus

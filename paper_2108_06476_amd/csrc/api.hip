@@ -312,27 +312,9 @@ dgx_status dgx_create(const dgx_config* cfg, void* hip_stream, dgx_handle* out) 
 
   // operator tables
   std::vector<double> T(TAB_SIZE, 0.0);
-  double x[16], w[16], D[256], Vinv[256];
-  if (!lgl_tables(h->N, x, w, D, Vinv)) {
+  if (!stage_tables(h->N, h->h, T.data())) {
     delete h;
     return DGX_EINVAL;
-  }
-  const int n = h->n;
-  for (int d = 0; d < 3; ++d) {
-    const double jac = 2.0 / h->h[d];
-    for (int i = 0; i < n; ++i)
-      for (int m = 0; m < n; ++m)
-        T[TAB_S + (d * TMAX + i) * TMAX + m] = (i == m) ? 0.0 : -jac * 2.0 * D[i * n + m];
-    T[TAB_LIFT + d * 2 + 0] = jac / w[0];
-    T[TAB_LIFT + d * 2 + 1] = -jac / w[h->N];
-    for (int i = 0; i < n; ++i) T[TAB_FV + d * TMAX + i] = -jac / w[i];
-    T[TAB_JAC + d] = jac;
-  }
-  for (int a = 0; a < n; ++a)
-    for (int i = 0; i < n; ++i) T[TAB_VINV + a * TMAX + i] = Vinv[a * n + i];
-  for (int i = 0; i < n; ++i) {
-    T[TAB_W + i] = w[i];
-    T[TAB_X + i] = x[i];
   }
 
   const int64_t nblk = (h->E + L->ne - 1) / L->ne;

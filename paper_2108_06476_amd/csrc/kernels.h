@@ -28,13 +28,14 @@ constexpr int TAB_SIZE = TAB_JAC + 3;
 enum { VOL_EC = 0, VOL_CENTRAL = 1, VOL_SHOCKCAP = 2, VOL_NONE = 4 };
 enum { EPI_RHS = 0, EPI_RK = 1 };
 
-template <int DIM, int N>
+// Element tiles: NE elements of NN nodes per block of up to BUDGET threads.
+template <int DIM, int N, int BUDGET = 256>
 struct Shape {
   static constexpr int n = N + 1;
   static constexpr int NN = DIM == 3 ? n * n * n : n * n;  // nodes per element
   static constexpr int NF = DIM == 3 ? n * n : n;          // nodes per face
   static constexpr int NV = DIM + 2;
-  static constexpr int NE = NN >= 256 ? 1 : 256 / NN;      // elements per block
+  static constexpr int NE = NN >= BUDGET ? 1 : BUDGET / NN;  // elements per block
   static constexpr int THREADS = ((NE * NN + 63) / 64) * 64;
 };
 
@@ -152,9 +153,9 @@ struct StageLds {
 // contributions [NV][NN], wave speeds [DIM][NN]) stays inside the element's own slot, so
 // elements never touch each other's scratch (with one element per wave, waves run without
 // block barriers).
-template <int DIM, int N, typename RT>
+template <int DIM, int N, typename RT, int BUDGET = 256>
 struct StageShape {
-  using S = Shape<DIM, N>;
+  using S = Shape<DIM, N, BUDGET>;
   static constexpr int NENN = S::NE * S::NN;
   static constexpr int SLOT_X = (int)sizeof(RT) * S::NV * S::NN;
   static constexpr int SLOT_S = 8 * DIM * S::NN;
@@ -333,17 +334,22 @@ struct StageArgs {
   int fvf;               // subcell FV flux (SURF_LLF or SURF_HLL)
 };
 
-template <int DIM, int N, int VOL, int EPI, typename RT>
-__global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_stage(StageArgs a, Geom g) {
-  using S = Shape<DIM, N>;
-  using SS = StageShape<DIM, N, RT>;
-  constexpr int NV = S::NV, NN = S::NN, NENN = SS::NENN;
-  constexpr bool CONS = (VOL == VOL_CENTRAL || VOL == VOL_SHOCKCAP);
-  __shared__ StageLds<RT, DIM, NENN, SS::XB, CONS> s;
-  __shared__ double sT[TAB_SIZE];
-  for (int i = threadIdx.x; i < TAB_SIZE; i += blockDim.x) sT[i] = g.tab[i];
+template <int DIM, int N, int VOL, typename RT, int BUDGET = 256>
+struct StageLdsOf {
+  using SS = StageShape<DIM, N, RT, BUDGET>;
+  using type = StageLds<RT, DIM, SS::NENN, SS::XB, (VOL == VOL_CENTRAL || VOL == VOL_SHOCKCAP)>;
+};
 
-  const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
+// One tile of elements (the body of the stage kernels).  sT holds the run's operator
+// tables in LDS; they are loaded by the caller and become visible at the first barrier.
+template <int DIM, int N, int VOL, int EPI, typename RT, int BUDGET>
+__device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, BUDGET>::type& s,
+                                           const double* sT, const StageArgs& a, const Geom& g,
+                                           int tile) {
+  using S = Shape<DIM, N, BUDGET>;
+  using SS = StageShape<DIM, N, RT, BUDGET>;
+  constexpr int NV = S::NV, NN = S::NN;
+  constexpr bool CONS = (VOL == VOL_CENTRAL || VOL == VOL_SHOCKCAP);
   const int le = threadIdx.x / NN;
   const int node = threadIdx.x - le * NN;
   const int e = tile * S::NE + le;
@@ -484,6 +490,14 @@ __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_stage(StageArgs a,
       }
     }
   }
+}
+
+template <int DIM, int N, int VOL, int EPI, typename RT>
+__global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_stage(StageArgs a, Geom g) {
+  __shared__ typename StageLdsOf<DIM, N, VOL, RT>::type s;
+  __shared__ double sT[TAB_SIZE];
+  for (int i = threadIdx.x; i < TAB_SIZE; i += blockDim.x) sT[i] = g.tab[i];
+  stage_tile<DIM, N, VOL, EPI, RT, 256>(s, sT, a, g, (int)xcd_tile(blockIdx.x, gridDim.x));
 }
 
 // --------------------------------------------------------------------------------------

@@ -10,6 +10,8 @@
 
 #include <cmath>
 
+#include "kernels.h"
+
 namespace dgx {
 
 static void legendre_all(int N, double x, double* P) {
@@ -74,6 +76,29 @@ bool lgl_tables(int N, double* x, double* w, double* D, double* Vinv) {
   }
   for (int a = 0; a < n; ++a)
     for (int i = 0; i < n; ++i) Vinv[a * n + i] = M[a][n + i];
+  return true;
+}
+
+bool stage_tables(int N, const double* h, double* T) {
+  double x[16], w[16], D[256], Vinv[256];
+  if (N < 1 || N >= TMAX || !lgl_tables(N, x, w, D, Vinv)) return false;
+  const int n = N + 1;
+  for (int d = 0; d < 3; ++d) {
+    const double jac = 2.0 / h[d];
+    for (int i = 0; i < n; ++i)
+      for (int m = 0; m < n; ++m)
+        T[TAB_S + (d * TMAX + i) * TMAX + m] = (i == m) ? 0.0 : -jac * 2.0 * D[i * n + m];
+    T[TAB_LIFT + d * 2 + 0] = jac / w[0];
+    T[TAB_LIFT + d * 2 + 1] = -jac / w[N];
+    for (int i = 0; i < n; ++i) T[TAB_FV + d * TMAX + i] = -jac / w[i];
+    T[TAB_JAC + d] = jac;
+  }
+  for (int a = 0; a < n; ++a)
+    for (int i = 0; i < n; ++i) T[TAB_VINV + a * TMAX + i] = Vinv[a * n + i];
+  for (int i = 0; i < n; ++i) {
+    T[TAB_W + i] = w[i];
+    T[TAB_X + i] = x[i];
+  }
   return true;
 }
 

@@ -24,7 +24,8 @@ EXPORTS = ["dgx_create", "dgx_destroy", "dgx_set_stream", "dgx_num_nodes", "dgx_
            "dgx_node_coords", "dgx_rhs", "dgx_indicator", "dgx_rhs_alpha", "dgx_max_dt",
            "dgx_step", "dgx_integrals", "dgx_check", "dgx_last_error", "dgx_profile_enable",
            "dgx_profile_read", "dgx_batch_create", "dgx_batch_destroy", "dgx_batch_num_nodes",
-           "dgx_batch_step", "dgx_batch_rhs", "dgx_batch_tune", "dgx_batch_last_error"]
+           "dgx_batch_step", "dgx_batch_rhs", "dgx_batch_tune", "dgx_batch_shape",
+           "dgx_batch_check", "dgx_batch_last_error"]
 
 
 class DgxError(RuntimeError):
@@ -80,6 +81,8 @@ def lib():
             "dgx_batch_step": ([vp, C.POINTER(vp), C.c_int32, C.c_double, vp], C.c_int),
             "dgx_batch_rhs": ([vp, C.POINTER(vp), C.POINTER(vp)], C.c_int),
             "dgx_batch_tune": ([vp, C.POINTER(vp), C.c_int32], C.c_int),
+            "dgx_batch_shape": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
+            "dgx_batch_check": ([vp, C.POINTER(C.c_int32)], C.c_int),
             "dgx_batch_last_error": ([vp], C.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -238,3 +241,65 @@ class Solver:
         name = C.c_char_p()
         self._call("dgx_profile_read", C.byref(avg), C.byref(n), C.byref(name))
         return avg.value, int(n.value), name.value.decode()
+
+
+class Batch:
+    """An ensemble of independent 3D runs (dgx_batch handle)."""
+
+    def __init__(self, configs):
+        L = lib()
+        arr = (Config * len(configs))(*[make_config(**c) for c in configs])
+        h = C.c_void_p()
+        st = L.dgx_batch_create(arr, len(configs), _stream(), C.byref(h))
+        if st != 0:
+            raise DgxError(st, "dgx_batch_create failed")
+        self._h = h
+        self.nruns = len(configs)
+        self.configs = list(configs)
+        self.num_nodes = [int(L.dgx_batch_num_nodes(h, r)) for r in range(self.nruns)]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dgx_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, ts, name):
+        if len(ts) != self.nruns:
+            raise ValueError(f"{name}: need {self.nruns} tensors")
+        return (C.c_void_p * self.nruns)(*[_ptr(t, f"{name}[{r}]", 5 * self.num_nodes[r])
+                                           for r, t in enumerate(ts)])
+
+    def _call(self, fname, *args):
+        st = getattr(lib(), fname)(self._h, *args)
+        if st != 0:
+            msg = lib().dgx_batch_last_error(self._h).decode()
+            raise DgxError(st, f"{fname}: {msg}")
+
+    def step(self, us, nsteps, cfl=0.5, t=None):
+        self._call("dgx_batch_step", self._ptrs(us, "u"), C.c_int32(nsteps), C.c_double(cfl),
+                   _ptr(t, "t", self.nruns) if t is not None else None)
+
+    def rhs(self, us, dus):
+        self._call("dgx_batch_rhs", self._ptrs(us, "u"), self._ptrs(dus, "du"))
+
+    def tune(self, us, budget_ms=2000):
+        self._call("dgx_batch_tune", self._ptrs(us, "u"), C.c_int32(budget_ms))
+        return self.shape()
+
+    def shape(self):
+        b, g = C.c_int32(0), C.c_int32(0)
+        self._call("dgx_batch_shape", C.byref(b), C.byref(g))
+        return b.value, g.value
+
+    def check(self):
+        f = C.c_int32(0)
+        st = lib().dgx_batch_check(self._h, C.byref(f))
+        if st not in (0, 4):
+            raise DgxError(st, lib().dgx_batch_last_error(self._h).decode())
+        return int(f.value)

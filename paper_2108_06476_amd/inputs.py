@@ -16,13 +16,26 @@ import numpy as np
 GAMMA = 1.4
 
 
+def _xp(a):
+    """NumPy, or torch for torch tensors (the same formulas evaluated where the data lives)."""
+    if type(a).__module__.startswith("torch"):
+        import torch
+        return torch
+    return np
+
+
 def prim_to_cons(rho, vel, p, gamma=GAMMA):
     """(rho, [v_1..v_d], p) -> u = (rho, rho v, p/(gamma-1) + rho |v|^2 / 2)."""
-    rho = np.asarray(rho, dtype=np.float64)
-    vel = [np.broadcast_to(np.asarray(v, dtype=np.float64), rho.shape) for v in vel]
-    p = np.broadcast_to(np.asarray(p, dtype=np.float64), rho.shape)
+    xp = _xp(rho)
+    if xp is np:
+        rho = np.asarray(rho, dtype=np.float64)
+        vel = [np.broadcast_to(np.asarray(v, dtype=np.float64), rho.shape) for v in vel]
+        p = np.broadcast_to(np.asarray(p, dtype=np.float64), rho.shape)
+    else:
+        vel = [v if _xp(v) is xp else xp.full_like(rho, float(v)) for v in vel]
+        p = p if _xp(p) is xp else xp.full_like(rho, float(p))
     v2 = sum(v * v for v in vel)
-    return np.stack([rho] + [rho * v for v in vel] + [p / (gamma - 1.0) + 0.5 * rho * v2])
+    return xp.stack([rho] + [rho * v for v in vel] + [p / (gamma - 1.0) + 0.5 * rho * v2])
 
 
 # --------------------------------------------------------------------------- workloads
@@ -85,18 +98,20 @@ def tgv(xyz, gamma=GAMMA, mach=0.1, perturb_seed=2108, perturb_amp=0.01, shift=(
     """Taylor-Green vortex, rho0 = V0 = 1: v = (sin x cos y cos z, -cos x sin y cos z, 0),
     p = 1/(gamma Ma^2) + (cos 2x + cos 2y)(cos 2z + 2)/16, optionally with
     rho <- rho (1 + amp * g / sum a_m), g = sum_m a_m sin(k_m . x + phi_m)."""
+    xp = _xp(xyz)
     x, y, z = (xyz[0] + shift[0], xyz[1] + shift[1], xyz[2] + shift[2])
-    rho = np.ones_like(x)
-    v1 = np.sin(x) * np.cos(y) * np.cos(z)
-    v2 = -np.cos(x) * np.sin(y) * np.cos(z)
-    v3 = np.zeros_like(x)
-    p = 1.0 / (gamma * mach * mach) + (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0) / 16.0
+    rho = xp.ones_like(x)
+    v1 = xp.sin(x) * xp.cos(y) * xp.cos(z)
+    v2 = -xp.cos(x) * xp.sin(y) * xp.cos(z)
+    v3 = xp.zeros_like(x)
+    p = 1.0 / (gamma * mach * mach) + (xp.cos(2 * x) + xp.cos(2 * y)) * (xp.cos(2 * z) + 2.0) / 16.0
     if perturb_seed is not None and perturb_amp != 0.0:
         ks, a, phi = tgv_perturbation_modes(perturb_seed)
-        g = np.zeros_like(x)
+        g = xp.zeros_like(x)
         for m in range(len(a)):
-            g += a[m] * np.sin(ks[m, 0] * x + ks[m, 1] * y + ks[m, 2] * z + phi[m])
-        rho = rho * (1.0 + perturb_amp * g / a.sum())
+            g += float(a[m]) * xp.sin(float(ks[m, 0]) * x + float(ks[m, 1]) * y +
+                                      float(ks[m, 2]) * z + float(phi[m]))
+        rho = rho * (1.0 + perturb_amp * g / float(a.sum()))
     return prim_to_cons(rho, [v1, v2, v3], p, gamma)
 
 
