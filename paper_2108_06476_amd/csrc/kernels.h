@@ -144,7 +144,7 @@ __device__ __forceinline__ void face_flux(int surf, const double (&uL)[DIM + 2],
 template <typename RT, int DIM, int NE_NN, int XB, bool CONS>
 struct StageLds {
   RT rho[NE_NN], v[DIM][NE_NN], p[NE_NN], beta[NE_NN];
-  double c[NE_NN];                    // sound speed (face fluxes)
+  double c[CONS ? NE_NN : 1];         // sound speed (subcell FV fluxes)
   alignas(16) unsigned char xb[XB];   // per element: partner contributions | wave speeds
   double u[CONS ? DIM + 2 : 1][CONS ? NE_NN : 1];
 };
@@ -164,11 +164,19 @@ struct StageShape {
   static constexpr int XB = S::NE * SLOT;
 };
 
+// LDS accumulation (ds_add): the partner's share of a pair flux.
+template <typename T>
+__device__ __forceinline__ void lds_add(T* p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Unique pairs along direction D.  In round r every node i pairs with i + r (mod n) and
-// evaluates the symmetric two-point flux once: it keeps S_{i,m} f and hands S_{m,i} f to
-// node m through LDS.  Rounds r = 1..(n-1)/2 cover every pair once; for even n the extra
-// round r = n/2 is computed by the nodes i < n/2 only.  All threads of the block pass every
-// barrier; `on` masks threads without an element.
+// evaluates the symmetric two-point flux once: it keeps S_{i,m} f and adds S_{m,i} f into
+// node m's LDS accumulator x (read back once after all directions).  Rounds r = 1..(n-1)/2
+// cover every pair once; for even n the extra round r = n/2 is computed by the nodes
+// i < n/2 only.  In a round every node receives exactly one share, and one wave's LDS
+// operations complete in issue order, so the sums are formed in a fixed order; elements
+// spread over several waves put a block barrier between rounds for the same reason.
 template <int DIM, int N, int D, int VOL, typename RT, typename L>
 __device__ __forceinline__ void volume_dir(const L& s, RT* __restrict__ x /* element slot */,
                                            bool on, int base,
@@ -220,15 +228,10 @@ __device__ __forceinline__ void volume_dir(const L& s, RT* __restrict__ x /* ele
 #pragma unroll
       for (int v = 0; v < DIM + 2; ++v) {
         acc[v] += cme * f[v];
-        x[v * NN + pn - base] = cpa * f[v];
+        lds_add(&x[v * NN + pn - base], cpa * f[v]);
       }
     }
-    elem_sync<DIM, N>();
-    if (on && (!half || id >= n / 2)) {
-#pragma unroll
-      for (int v = 0; v < DIM + 2; ++v) acc[v] += x[v * NN + node];
-    }
-    elem_sync<DIM, N>();
+    if constexpr (!WaveElem<DIM, N>::value) __syncthreads();
   }
 }
 
@@ -276,11 +279,10 @@ __device__ __forceinline__ void fv_dir(const L& s, int fvf, int base, int node, 
 // across that face and lifts it, +(2/h_D)/w_0 F* (minus) or -(2/h_D)/w_N F* (plus).  Both
 // elements of an interface evaluate it from the same (left, right) states in the same
 // order, so they obtain the same value.
+// Issue the loads of the neighbour's node across the face in direction D (if any).
 template <int DIM, int N, int D>
-__device__ __forceinline__ void surface_dir(const double* __restrict__ u, const Geom& g, int surf,
-                                            int e, const int (&ec)[3], int node,
-                                            const double (&um)[DIM + 2], const Prim<double>& qm,
-                                            const double* sL, double (&R)[DIM + 2]) {
+__device__ __forceinline__ void face_load(const double* __restrict__ u, const Geom& g, int e,
+                                          const int (&ec)[3], int node, double (&un)[DIM + 2]) {
   using S = Shape<DIM, N>;
   constexpr int n = S::n, NN = S::NN, NV = S::NV, st = Stride<D, n>::value;
   const int id = (node / st) % n;
@@ -289,33 +291,58 @@ __device__ __forceinline__ void surface_dir(const double* __restrict__ u, const 
   const int oth = plus ? node - N * st : node + N * st;
   const int enb = elem_nb(g, e, ec, D, plus ? 1 : -1);
   const unsigned ENN = (unsigned)g.E * NN;
-  double un[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) un[v] = u[v * ENN + (unsigned)enb * NN + oth];
+}
+
+template <int DIM, int N, int D>
+__device__ __forceinline__ void surface_dir(const Geom& g, int surf, int node,
+                                            const double (&um)[DIM + 2], const Prim<double>& qm,
+                                            const double (&un)[DIM + 2], const double* sL,
+                                            double (&R)[DIM + 2]) {
+  using S = Shape<DIM, N>;
+  constexpr int n = S::n, NV = S::NV, st = Stride<D, n>::value;
+  const int id = (node / st) % n;
+  if (id != 0 && id != N) return;
+  const bool plus = (id == N);
   Prim<double> qn;
-  if (!cons_to_prim<DIM>(un, g.gamma, qn)) *g.flag = 1;
-  double uL[NV], uR[NV];
-  Prim<double> qL, qR;
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    uL[v] = plus ? um[v] : un[v];
-    uR[v] = plus ? un[v] : um[v];
-  }
-  qL.rho = plus ? qm.rho : qn.rho;
-  qR.rho = plus ? qn.rho : qm.rho;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    qL.v[k] = plus ? qm.v[k] : qn.v[k];
-    qR.v[k] = plus ? qn.v[k] : qm.v[k];
-  }
-  qL.p = plus ? qm.p : qn.p;
-  qR.p = plus ? qn.p : qm.p;
-  qL.beta = plus ? qm.beta : qn.beta;
-  qR.beta = plus ? qn.beta : qm.beta;
-  qL.c = plus ? qm.c : qn.c;
-  qR.c = plus ? qn.c : qm.c;
+  const bool ok = surf == SURF_EC ? cons_to_prim<DIM, true>(un, g.gamma, qn)
+                                  : cons_to_prim<DIM, false>(un, g.gamma, qn);
+  if (!ok) *g.flag = 1;
   double F[NV];
-  face_flux<DIM, D>(surf, uL, qL, uR, qR, g.gamma, F);
+  if (surf == SURF_LLF) {
+    // (f_L + f_R)/2 - lambda (u_R - u_L)/2 from (own, neighbour): the sign s of the jump
+    // term makes both elements' evaluations identical bit for bit
+    double fo[NV], fn[NV];
+    phys_flux<DIM, D>(um, qm, fo);
+    phys_flux<DIM, D>(un, qn, fn);
+    const double lam = fmax(fabs(qm.v[D]) + qm.c, fabs(qn.v[D]) + qn.c);
+    const double hl = (plus ? 0.5 : -0.5) * lam;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = 0.5 * (fo[v] + fn[v]) - hl * (un[v] - um[v]);
+  } else if (surf == SURF_EC) {
+    ec_flux_sym<DIM, D>(qm, qn, 1.0 / (g.gamma - 1.0), F);
+  } else {
+    double uL[NV], uR[NV];
+    Prim<double> qL, qR;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      uL[v] = plus ? um[v] : un[v];
+      uR[v] = plus ? un[v] : um[v];
+    }
+    qL.rho = plus ? qm.rho : qn.rho;
+    qR.rho = plus ? qn.rho : qm.rho;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      qL.v[k] = plus ? qm.v[k] : qn.v[k];
+      qR.v[k] = plus ? qn.v[k] : qm.v[k];
+    }
+    qL.p = plus ? qm.p : qn.p;
+    qR.p = plus ? qn.p : qm.p;
+    qL.c = plus ? qm.c : qn.c;
+    qR.c = plus ? qn.c : qm.c;
+    hll_flux<DIM, D>(uL, qL, uR, qR, g.gamma, F);
+  }
   const double c = plus ? sL[2 * D + 1] : sL[2 * D];
 #pragma unroll
   for (int v = 0; v < NV; ++v) R[v] += c * F[v];
@@ -360,13 +387,21 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   const unsigned own_ix = (unsigned)e * NN + node;
 
   double um[NV];
+  double unb[DIM][NV];   // neighbours' face-node states, loaded up front
   Prim<double> qd;
   if (active) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) um[v] = a.uin[v * ENN + own_ix];
+    if (a.surf != SURF_NONE) {
+      int ec[3];
+      elem_xyz(g, e, ec);
+      face_load<DIM, N, 0>(a.uin, g, e, ec, node, unb[0]);
+      face_load<DIM, N, 1>(a.uin, g, e, ec, node, unb[1]);
+      if constexpr (DIM == 3) face_load<DIM, N, 2>(a.uin, g, e, ec, node, unb[2]);
+    }
     if (!cons_to_prim<DIM>(um, g.gamma, qd)) *g.flag = 1;
     const int li = base + node;
-    s.c[li] = qd.c;
+    if constexpr (CONS) s.c[li] = qd.c;
     s.rho[li] = (RT)qd.rho;
 #pragma unroll
     for (int k = 0; k < DIM; ++k) s.v[k][li] = (RT)qd.v[k];
@@ -383,18 +418,21 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     qd.v[0] = qd.v[1] = qd.v[2] = 0.0;
   }
 
+  if (inb) {   // zero this node's partner-share accumulator
+    RT* x = reinterpret_cast<RT*>(s.xb + le * SS::SLOT);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v * NN + node] = RT(0);
+  }
   double R[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) R[v] = 0.0;
-  __syncthreads();   // tables and staged nodes visible
+  __syncthreads();   // tables, staged nodes and zeroed accumulators visible
 
   // ---- surface: each boundary node's face flux, lifted onto the node
   if (a.surf != SURF_NONE && active) {
-    int ec[3];
-    elem_xyz(g, e, ec);
-    surface_dir<DIM, N, 0>(a.uin, g, a.surf, e, ec, node, um, qd, sT + TAB_LIFT, R);
-    surface_dir<DIM, N, 1>(a.uin, g, a.surf, e, ec, node, um, qd, sT + TAB_LIFT, R);
-    if constexpr (DIM == 3) surface_dir<DIM, N, 2>(a.uin, g, a.surf, e, ec, node, um, qd, sT + TAB_LIFT, R);
+    surface_dir<DIM, N, 0>(g, a.surf, node, um, qd, unb[0], sT + TAB_LIFT, R);
+    surface_dir<DIM, N, 1>(g, a.surf, node, um, qd, unb[1], sT + TAB_LIFT, R);
+    if constexpr (DIM == 3) surface_dir<DIM, N, 2>(g, a.surf, node, um, qd, unb[2], sT + TAB_LIFT, R);
   }
 
   // ---- volume
@@ -407,14 +445,20 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     me.p = (RT)qd.p;
     me.beta = (RT)qd.beta;
     const RT inv_gm1 = (RT)(1.0 / (g.gamma - 1.0));
+    // float64 without blending: the surface terms seed the volume accumulator (fewer live
+    // registers through the pair rounds)
+    constexpr bool SEED = (VOL != VOL_SHOCKCAP) && sizeof(RT) == 8;
     RT acc[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = RT(0);
+    for (int v = 0; v < NV; ++v) acc[v] = SEED ? (RT)R[v] : RT(0);
     volume_dir<DIM, N, 0, VOL, RT>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
     volume_dir<DIM, N, 1, VOL, RT>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
     if constexpr (DIM == 3)
       volume_dir<DIM, N, 2, VOL, RT>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
+    elem_sync<DIM, N>();   // every partner share has landed
     if (active) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] += x[v * NN + node];
       if constexpr (VOL == VOL_SHOCKCAP) {
         const double al = a.alpha[e];
         if (al != 0.0) {
@@ -430,6 +474,9 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
 #pragma unroll
           for (int v = 0; v < NV; ++v) R[v] += (double)acc[v];
         }
+      } else if constexpr (SEED) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) R[v] = (double)acc[v];
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) R[v] += (double)acc[v];
@@ -447,12 +494,19 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     double un[NV];
     if (active) {
       const double dt = *a.dt;
+      double kv[NV];
+      if (a.A == 0.0) {   // first stage: k is not read (uniform branch)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) kv[v] = dt * R[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) kv[v] = a.A * a.k[v * ENN + own_ix] + dt * R[v];
+      }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const unsigned ix = v * ENN + own_ix;
-        const double kv = (a.A == 0.0) ? dt * R[v] : a.A * a.k[ix] + dt * R[v];
-        a.k[ix] = kv;
-        un[v] = um[v] + a.B * kv;
+        a.k[ix] = kv[v];
+        un[v] = um[v] + a.B * kv[v];
         a.uout[ix] = un[v];
       }
     }

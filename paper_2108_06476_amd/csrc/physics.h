@@ -26,6 +26,20 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, e, r);
 }
 
+// sqrt(x) for normal x > 0: the hardware reciprocal square root, one Newton step on
+// (g, h) = (sqrt x, 1/(2 sqrt x)) and two residual corrections g += (x - g^2) h.
+__device__ __forceinline__ double sqrt_pos(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  const double r = fma(-g, h, 0.5);
+  g = fma(g, r, g);
+  h = fma(h, r, h);
+  double d = fma(-g, g, x);
+  g = fma(d, h, g);
+  d = fma(-g, g, x);
+  return fma(d, h, g);
+}
+
 // Logarithmic mean {{a}}_ln = (b - a)/(ln b - ln a) and its reciprocal.  With
 // z = (b - a)/(b + a), ln(b/a) = 2 artanh z, so {{a}}_ln = (a + b)/2 * z/artanh(z) and
 // 1/{{a}}_ln = 2/(a + b) * artanh(z)/z.  Below z^2 = 1e-4 (the threshold of the efficiency
@@ -37,7 +51,8 @@ __device__ __forceinline__ double ln_mean(double a, double b) {
   const double z = d * r, z2 = z * z;
   if (z2 < 1.0e-4)
     return 0.5 * s * (1.0 + z2 * (-1.0 / 3.0 + z2 * (-4.0 / 45.0 + z2 * (-44.0 / 945.0))));
-  return d / log(b / a);
+  const double hi = fmax(a, b), lo = fmin(a, b);   // symmetric in (a, b), bit for bit
+  return (hi - lo) / log(hi / lo);
 }
 
 __device__ __forceinline__ double inv_ln_mean(double a, double b) {
@@ -46,7 +61,8 @@ __device__ __forceinline__ double inv_ln_mean(double a, double b) {
   const double z = d * r, z2 = z * z;
   if (z2 < 1.0e-4)
     return 2.0 * r * (1.0 + z2 * (1.0 / 3.0 + z2 * (1.0 / 5.0 + z2 * (1.0 / 7.0))));
-  return log(b / a) / d;
+  const double hi = fmax(a, b), lo = fmin(a, b);
+  return log(hi / lo) / (hi - lo);
 }
 
 // Mixed precision: the near-equal branch is evaluated in float64, the log branch in
@@ -69,8 +85,9 @@ __device__ __forceinline__ float inv_ln_mean(float a, float b) {
   return __logf(b / a) / (b - a);
 }
 
-// Conserved -> primitive.  Returns false for a non-physical state.
-template <int DIM>
+// Conserved -> primitive (beta = rho/p only when BETA).  Returns false for a non-physical
+// state.
+template <int DIM, bool BETA = true>
 __device__ __forceinline__ bool cons_to_prim(const double (&u)[DIM + 2], double gamma,
                                              Prim<double>& q) {
   q.rho = u[0];
@@ -84,8 +101,8 @@ __device__ __forceinline__ bool cons_to_prim(const double (&u)[DIM + 2], double 
     v2 += q.v[k] * q.v[k];
   }
   q.p = (gamma - 1.0) * (u[DIM + 1] - 0.5 * u[0] * v2);
-  q.beta = q.rho * rcp_nr(q.p);
-  q.c = sqrt(gamma * q.p * inv);
+  q.beta = BETA ? q.rho * rcp_nr(q.p) : 0.0;
+  q.c = sqrt_pos(gamma * q.p * inv);
   return (q.rho > 0.0) && (q.p > 0.0) && (q.p < 1.0e300) && (q.rho < 1.0e300);
 }
 
@@ -107,6 +124,25 @@ __device__ __forceinline__ void ec_flux(const Prim<T>& L, const Prim<T>& R, T in
 #pragma unroll
   for (int k = 0; k < DIM; ++k) f[1 + k] = frho * (half * (L.v[k] + R.v[k])) + (k == D ? pavg : T(0));
   f[DIM + 1] = frho * (ibeta * inv_gm1 + half * vLvR) + half * (L.p * R.v[D] + R.p * L.v[D]);
+}
+
+// The EC flux with its state-pair products kept apart, so that f#(L, R) and f#(R, L) agree
+// bit for bit (both elements of an interface evaluate it).
+template <int DIM, int D>
+__device__ __forceinline__ void ec_flux_sym(const Prim<double>& L, const Prim<double>& R,
+                                            double inv_gm1, double (&f)[DIM + 2]) {
+  const double rho_ln = ln_mean(L.rho, R.rho);
+  const double ibeta = inv_ln_mean(L.beta, R.beta);
+  double vLvR = L.v[0] * R.v[0];
+#pragma unroll
+  for (int k = 1; k < DIM; ++k) vLvR += L.v[k] * R.v[k];
+  const double frho = rho_ln * (0.5 * (L.v[D] + R.v[D]));
+  const double pavg = 0.5 * (L.p + R.p);
+  f[0] = frho;
+#pragma unroll
+  for (int k = 0; k < DIM; ++k) f[1 + k] = frho * (0.5 * (L.v[k] + R.v[k])) + (k == D ? pavg : 0.0);
+  const double pv = __dadd_rn(__dmul_rn(L.p, R.v[D]), __dmul_rn(R.p, L.v[D]));
+  f[DIM + 1] = frho * (ibeta * inv_gm1 + 0.5 * vLvR) + 0.5 * pv;
 }
 
 // Physical flux f^D(u) = (rho v_D, rho v_D v + p e_D, v_D (rho E + p)).
