@@ -131,9 +131,11 @@ def main():
     secs, prof = time_steps(s, u, args.steps, args.warmup, profile=True)
     value = args.steps * 5 * nodes / secs
     avg_ms, launches, kname = prof
-    # dominant kernel: fused volume + lift + Jacobian + RK stage update.  Algorithmic bytes
-    # per node and stage: read u and k, write k and u (4 x 5 float64 = 160 B).
-    alg_bytes = 160.0 * nodes
+    # dominant kernel: fused volume + surface + lift + Jacobian + RK stage update.
+    # Algorithmic bytes per node, averaged over the five stages of a step: each stage reads
+    # u and writes k and u; stages 2-5 also read k (first stage: k = dt R), so the five
+    # stages move 3 + 4 * 4 = 19 arrays of 5 float64 = 760 B, 152 B per launch.
+    alg_bytes = 152.0 * nodes
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -141,8 +141,10 @@ dgx_status dgx_check(dgx_handle h, int32_t *flag);
 /* The handle's last error message (host string owned by the handle). */
 const char *dgx_last_error(dgx_handle h);
 
-/* Kernel timing of the last dgx_rhs / dgx_step launch sequence, for benchmarks:
- * enables HIP-event timing of the dominant kernel on the handle's stream. */
+/* Kernel timing for benchmarks: enables HIP-event timing of the dominant (stage) kernel on
+ * the handle's stream.  One event pair brackets each run of back-to-back stage launches
+ * (the five stages of an RK step; a single launch where indicator kernels sit between
+ * stages, and for dgx_rhs), so the time includes the launch gaps inside a run. */
 dgx_status dgx_profile_enable(dgx_handle h, int32_t on);
 /* Average duration in milliseconds of the timed kernel's launches since enable, and
  * its name (host string). */

@@ -69,20 +69,13 @@ static const double CK_B[5] = {1432997174477.0 / 9575080441755.0,
                                2277821191437.0 / 14882151754819.0};
 
 // dt = cfl * 2 / ((N+1) * max partial); t += dt
-__global__ __launch_bounds__(256) void k_dt_final(const double* __restrict__ partial, int64_t np,
-                                                  double cfl, double n1, double* __restrict__ dt,
-                                                  double* __restrict__ t) {
-  __shared__ double s[256];
-  double m = 0.0;
-  for (int64_t i = threadIdx.x; i < np; i += 256) m = fmax(m, partial[i]);
-  s[threadIdx.x] = m;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + h]);
-    __syncthreads();
-  }
+__global__ __launch_bounds__(1024) void k_dt_final(const double* __restrict__ partial, int64_t np,
+                                                   double cfl, double n1, double* __restrict__ dt,
+                                                   double* __restrict__ t) {
+  __shared__ double s[16];
+  const double m = block_max<1024>(partial, np, s);
   if (threadIdx.x == 0) {
-    const double d = cfl * 2.0 / (n1 * s[0]);
+    const double d = cfl * 2.0 / (n1 * m);
     *dt = d;
     if (t) *t += d;
   }
@@ -149,6 +142,7 @@ struct dgx_solver {
   bool prof = false;
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
+  std::vector<int> ev_count;   // stage launches inside each event pair
   int64_t launches = 0;
   double prof_ms = 0.0;
 };
@@ -200,10 +194,12 @@ dgx_status check_dev(dgx_handle h, const void* p, size_t bytes, const char* name
 
 size_t state_bytes(dgx_handle h) { return sizeof(double) * (size_t)h->NV * h->E * h->NN; }
 
-// Launch one stage kernel, optionally bracketed by timing events (the dominant kernel).
-hipError_t launch_stage(dgx_handle h, const StageArgs& a, int epi) {
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (h->prof) {
+// Timing of the dominant kernel: one event pair brackets a run of consecutive stage
+// launches (an event recorded between two kernels leaves the stream idle for microseconds),
+// and the pair's time is shared by the launches inside it.
+hipError_t launch_stage(dgx_handle h, const StageArgs& a, int epi, bool last) {
+  const size_t pair = h->ev_used / 2;
+  if (h->prof && h->ev_count.size() <= pair) {   // open a bracket
     if (h->ev_used + 2 > h->ev.size()) {
       for (int i = 0; i < 2; ++i) {
         hipEvent_t ev;
@@ -212,15 +208,17 @@ hipError_t launch_stage(dgx_handle h, const StageArgs& a, int epi) {
         h->ev.push_back(ev);
       }
     }
-    e0 = h->ev[h->ev_used];
-    e1 = h->ev[h->ev_used + 1];
-    h->ev_used += 2;
-    hipError_t r = hipEventRecord(e0, h->stream);
+    h->ev_count.push_back(0);
+    hipError_t r = hipEventRecord(h->ev[h->ev_used], h->stream);
     if (r != hipSuccess) return r;
   }
   hipError_t r = h->L->stage(h->stream, a, h->g, h->cfg.volume, epi, h->cfg.precision);
-  if (r != hipSuccess) return r;
-  if (h->prof) r = hipEventRecord(e1, h->stream);
+  if (r != hipSuccess || !h->prof) return r;
+  h->ev_count[pair] += 1;
+  if (last) {   // close it
+    r = hipEventRecord(h->ev[h->ev_used + 1], h->stream);
+    h->ev_used += 2;
+  }
   return r;
 }
 
@@ -257,7 +255,7 @@ dgx_status enqueue_rhs(dgx_handle h, const double* u, double* du, const double* 
   }
   StageArgs a = stage_args(h, u, alpha);
   a.du = du;
-  HIPCHK(h, launch_stage(h, a, EPI_RHS));
+  HIPCHK(h, launch_stage(h, a, EPI_RHS, true));
   return DGX_OK;
 }
 
@@ -421,7 +419,7 @@ dgx_status dgx_max_dt(dgx_handle h, const double* u, double cfl, double* dt) {
   CHKDEV(h, u, state_bytes(h), "u");
   CHKDEV(h, dt, sizeof(double), "dt");
   HIPCHK(h, h->L->maxspeed(h->stream, u, h->partial, h->g));
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, h->stream, h->partial, h->npart, cfl,
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, h->stream, h->partial, h->npart, cfl,
                      (double)(h->N + 1), dt, (double*)nullptr);
   HIPCHK(h, hipGetLastError());
   return DGX_OK;
@@ -444,7 +442,7 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
   for (int s = 0; s < nsteps; ++s) {
     if (adaptive) {
       // partials: from the wave-speed pass (first step) or from the last stage of the step before
-      hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, h->stream, h->partial, h->npart, cfl,
+      hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, h->stream, h->partial, h->npart, cfl,
                          (double)(h->N + 1), h->dt, t);
     } else {
       hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, h->stream, dt_fixed, h->dt, t);
@@ -463,7 +461,8 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
       a.A = CK_A[st];
       a.B = CK_B[st];
       a.speed = (adaptive && st == 4 && s + 1 < nsteps) ? h->partial : nullptr;
-      HIPCHK(h, launch_stage(h, a, EPI_RK));
+      // stages of one step run back to back unless indicator kernels sit between them
+      HIPCHK(h, launch_stage(h, a, EPI_RK, st == 4 || alpha != nullptr));
       cur = 1 - cur;
     }
   }
@@ -505,6 +504,7 @@ dgx_status dgx_profile_enable(dgx_handle h, int32_t on) {
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->prof = on != 0;
   h->ev_used = 0;
+  h->ev_count.clear();
   h->launches = 0;
   h->prof_ms = 0.0;
   return DGX_OK;
@@ -517,9 +517,10 @@ dgx_status dgx_profile_read(dgx_handle h, double* avg_ms, int64_t* launches, con
     float ms = 0.f;
     HIPCHK(h, hipEventElapsedTime(&ms, h->ev[i], h->ev[i + 1]));
     h->prof_ms += ms;
-    h->launches += 1;
+    h->launches += h->ev_count[i / 2];
   }
   h->ev_used = 0;
+  h->ev_count.clear();
   if (avg_ms) *avg_ms = h->launches ? h->prof_ms / h->launches : 0.0;
   if (launches) *launches = h->launches;
   if (name) *name = h->L->volume_name;

@@ -165,19 +165,12 @@ __global__ __launch_bounds__(BUDGET) void k_batch_maxspeed(BatchLaunch b) {
 }
 
 // One block per run: dt = cfl * 2 / ((N+1) * max_e speed[e]); t += dt.
-__global__ __launch_bounds__(256) void k_batch_dt(const RunDesc* __restrict__ runs, double cfl) {
-  __shared__ double s[256];
+__global__ __launch_bounds__(512) void k_batch_dt(const RunDesc* __restrict__ runs, double cfl) {
+  __shared__ double s[8];
   const RunDesc d = runs[blockIdx.x];
-  double m = 0.0;
-  for (int i = threadIdx.x; i < d.E; i += 256) m = fmax(m, d.speed[i]);
-  s[threadIdx.x] = m;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + h]);
-    __syncthreads();
-  }
+  const double m = block_max<512>(d.speed, d.E, s);
   if (threadIdx.x == 0) {
-    const double dt = cfl * 2.0 / ((d.N + 1.0) * s[0]);
+    const double dt = cfl * 2.0 / ((d.N + 1.0) * m);
     *d.dt = dt;
     if (d.t) *d.t += dt;
   }
@@ -237,7 +230,7 @@ hipError_t batch_maxspeed(hipStream_t st, const BatchLaunch& b, int budget, int 
 }
 
 hipError_t batch_dt(hipStream_t st, const RunDesc* runs, int nruns, double cfl) {
-  hipLaunchKernelGGL(k_batch_dt, dim3(nruns), dim3(256), 0, st, runs, cfl);
+  hipLaunchKernelGGL(k_batch_dt, dim3(nruns), dim3(512), 0, st, runs, cfl);
   return hipGetLastError();
 }
 

@@ -103,6 +103,31 @@ struct WaveElem {
   static constexpr bool value = Shape<DIM, N>::NN == 64;
 };
 
+// One DPP move of a double (two 32-bit halves with the same control): lanes that the row
+// mask leaves out keep `old`.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double old, double src) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(old), __double2loint(src), CTRL,
+                                             ROW_MASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(old), __double2hiint(src), CTRL,
+                                             ROW_MASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Max over the 64 lanes of a wave (all active), valid in lane 63: swaps within quads, the
+// half-row and row mirrors (every lane of a row of 16 then holds the row's max), then the
+// broadcasts of lane 15 into row 1 and row 3 and of lane 31 into rows 2 and 3.  Register
+// moves only, no LDS round trips.
+__device__ __forceinline__ double wave_max_lane63(double x) {
+  x = fmax(x, dpp_f64<0xB1, 0xF>(x, x));    // quad_perm [1,0,3,2]
+  x = fmax(x, dpp_f64<0x4E, 0xF>(x, x));    // quad_perm [2,3,0,1]
+  x = fmax(x, dpp_f64<0x141, 0xF>(x, x));   // row_half_mirror
+  x = fmax(x, dpp_f64<0x140, 0xF>(x, x));   // row_mirror
+  x = fmax(x, dpp_f64<0x142, 0xA>(x, x));   // row_bcast:15 into rows 1 and 3
+  x = fmax(x, dpp_f64<0x143, 0xC>(x, x));   // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 template <int DIM, int N>
 __device__ __forceinline__ void elem_sync() {
   if constexpr (WaveElem<DIM, N>::value) wave_sync();
@@ -157,16 +182,18 @@ template <int DIM, int N, typename RT, int BUDGET = 256>
 struct StageShape {
   using S = Shape<DIM, N, BUDGET>;
   static constexpr int NENN = S::NE * S::NN;
-  static constexpr int SLOT_X = (int)sizeof(RT) * S::NV * S::NN;
+  static constexpr int SLOT_X = 8 * S::NV * S::NN;   // float64 partner shares
   static constexpr int SLOT_S = 8 * DIM * S::NN;
   static constexpr int SLOT0 = SLOT_X > SLOT_S ? SLOT_X : SLOT_S;
   static constexpr int SLOT = (SLOT0 + 15) / 16 * 16;
   static constexpr int XB = S::NE * SLOT;
 };
 
-// LDS accumulation (ds_add): the partner's share of a pair flux.
-template <typename T>
-__device__ __forceinline__ void lds_add(T* p, T v) {
+// LDS accumulation (ds_add_f64): the partner's share of a pair flux.  The shares are
+// summed in float64 also for float32 fluxes: on gfx950 an LDS float32 atomic add costs
+// about ten times the LDS cycles of the float64 one, and the float64 sum is the more
+// accurate of the two.
+__device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
@@ -178,7 +205,7 @@ __device__ __forceinline__ void lds_add(T* p, T v) {
 // operations complete in issue order, so the sums are formed in a fixed order; elements
 // spread over several waves put a block barrier between rounds for the same reason.
 template <int DIM, int N, int D, int VOL, typename RT, typename L>
-__device__ __forceinline__ void volume_dir(const L& s, RT* __restrict__ x /* element slot */,
+__device__ __forceinline__ void volume_dir(const L& s, double* __restrict__ x /* element slot */,
                                            bool on, int base,
                                            int node, const Prim<RT>& me,
                                            const double (&ume)[DIM + 2], const double* sS,
@@ -228,7 +255,7 @@ __device__ __forceinline__ void volume_dir(const L& s, RT* __restrict__ x /* ele
 #pragma unroll
       for (int v = 0; v < DIM + 2; ++v) {
         acc[v] += cme * f[v];
-        lds_add(&x[v * NN + pn - base], cpa * f[v]);
+        lds_add(&x[v * NN + pn - base], (double)(cpa * f[v]));
       }
     }
     if constexpr (!WaveElem<DIM, N>::value) __syncthreads();
@@ -419,9 +446,9 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   }
 
   if (inb) {   // zero this node's partner-share accumulator
-    RT* x = reinterpret_cast<RT*>(s.xb + le * SS::SLOT);
+    double* x = reinterpret_cast<double*>(s.xb + le * SS::SLOT);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) x[v * NN + node] = RT(0);
+    for (int v = 0; v < NV; ++v) x[v * NN + node] = 0.0;
   }
   double R[NV];
 #pragma unroll
@@ -437,7 +464,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
 
   // ---- volume
   if constexpr (VOL != VOL_NONE) {
-    RT* x = reinterpret_cast<RT*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);
+    double* x = reinterpret_cast<double*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);
     Prim<RT> me;
     me.rho = (RT)qd.rho;
 #pragma unroll
@@ -458,7 +485,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     elem_sync<DIM, N>();   // every partner share has landed
     if (active) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] += x[v * NN + node];
+      for (int v = 0; v < NV; ++v) acc[v] += (RT)x[v * NN + node];
       if constexpr (VOL == VOL_SHOCKCAP) {
         const double al = a.alpha[e];
         if (al != 0.0) {
@@ -513,34 +540,45 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     if (a.speed != nullptr) {
       // per element: sum_d (2/h_d) max over its nodes of |v_d| + c of the new state, one
       // partial of the next CFL time step per element
-      constexpr int P2 = NN <= 4 ? 4 : NN <= 16 ? 16 : NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
-      double* sp = reinterpret_cast<double*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);   // [DIM][NN]
-      elem_sync<DIM, N>();
-      if (inb) {
-        if (active) {
+      if constexpr (WaveElem<DIM, N>::value) {
+        if (active) {   // uniform per wave: the element is the wave
           Prim<double> q;
-          if (!cons_to_prim<DIM>(un, g.gamma, q)) *g.flag = 1;
+          if (!cons_to_prim<DIM, false>(un, g.gamma, q)) *g.flag = 1;
+          double lam = 0.0;
 #pragma unroll
-          for (int d = 0; d < DIM; ++d) sp[d * NN + node] = fabs(q.v[d]) + q.c;
-        } else {
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) sp[d * NN + node] = 0.0;
+          for (int d = 0; d < DIM; ++d) lam += sT[TAB_JAC + d] * wave_max_lane63(fabs(q.v[d]) + q.c);
+          if (node == NN - 1) a.speed[e] = lam;
         }
-      }
-      elem_sync<DIM, N>();
-      for (int h = P2 / 2; h > 0; h >>= 1) {
-        if (inb && node < h && node + h < NN) {
+      } else {
+        constexpr int P2 = NN <= 4 ? 4 : NN <= 16 ? 16 : NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
+        double* sp = reinterpret_cast<double*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);   // [DIM][NN]
+        __syncthreads();
+        if (inb) {
+          if (active) {
+            Prim<double> q;
+            if (!cons_to_prim<DIM, false>(un, g.gamma, q)) *g.flag = 1;
 #pragma unroll
-          for (int d = 0; d < DIM; ++d)
-            sp[d * NN + node] = fmax(sp[d * NN + node], sp[d * NN + node + h]);
+            for (int d = 0; d < DIM; ++d) sp[d * NN + node] = fabs(q.v[d]) + q.c;
+          } else {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) sp[d * NN + node] = 0.0;
+          }
         }
-        elem_sync<DIM, N>();
-      }
-      if (active && node == 0) {
-        double lam = 0.0;
+        __syncthreads();
+        for (int h = P2 / 2; h > 0; h >>= 1) {
+          if (inb && node < h && node + h < NN) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) lam += sT[TAB_JAC + d] * sp[d * NN];
-        a.speed[e] = lam;
+            for (int d = 0; d < DIM; ++d)
+              sp[d * NN + node] = fmax(sp[d * NN + node], sp[d * NN + node + h]);
+          }
+          __syncthreads();
+        }
+        if (active && node == 0) {
+          double lam = 0.0;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) lam += sT[TAB_JAC + d] * sp[d * NN];
+          a.speed[e] = lam;
+        }
       }
     }
   }
@@ -645,6 +683,35 @@ __global__ __launch_bounds__(256) void k_smooth(const double* __restrict__ ar,
     }
   }
   alpha[e] = a;
+}
+
+// --------------------------------------------------------------------------------------
+// Max of p[0, n) over one block of T threads (T a multiple of 64), valid in thread 0.
+// Eight independent loads per thread are kept in flight: the pass reads a few hundred KB
+// from a single CU, so it is bound by load latency, not bandwidth.  max is exact, so the
+// result does not depend on the order.  s: LDS scratch of T / 64 doubles.
+// --------------------------------------------------------------------------------------
+template <int T>
+__device__ double block_max(const double* __restrict__ p, int64_t n, double* s) {
+  static_assert(T % 64 == 0 && T <= 4096, "block of whole waves");
+  double m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int64_t i = threadIdx.x;
+  for (; i + 7 * T < n; i += 8 * T) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) m[k] = fmax(m[k], p[i + k * T]);
+  }
+  for (; i < n; i += T) m[0] = fmax(m[0], p[i]);
+  double r = fmax(fmax(fmax(m[0], m[1]), fmax(m[2], m[3])), fmax(fmax(m[4], m[5]), fmax(m[6], m[7])));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = r;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    r = (int)threadIdx.x < T / 64 ? s[threadIdx.x] : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
+  }
+  return r;
 }
 
 // --------------------------------------------------------------------------------------
