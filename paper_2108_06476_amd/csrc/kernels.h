@@ -200,11 +200,12 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
 // Unique pairs along direction D.  In round r every node i pairs with i + r (mod n) and
 // evaluates the symmetric two-point flux once: it keeps S_{i,m} f and adds S_{m,i} f into
 // node m's LDS accumulator x (read back once after all directions).  Rounds r = 1..(n-1)/2
-// cover every pair once; for even n the extra round r = n/2 is computed by the nodes
-// i < n/2 only.  In a round every node receives exactly one share, and one wave's LDS
+// cover every pair once; for even n the extra round r = n/2 (HALF) is computed by the
+// nodes i < n/2 only, unless the caller packs it with another direction's.  In a round
+// every node receives at most one share, and one wave's LDS
 // operations complete in issue order, so the sums are formed in a fixed order; elements
 // spread over several waves put a block barrier between rounds for the same reason.
-template <int DIM, int N, int D, int VOL, typename RT, typename L>
+template <int DIM, int N, int D, int VOL, typename RT, bool HALF, typename L>
 __device__ __forceinline__ void volume_dir(const L& s, double* __restrict__ x /* element slot */,
                                            bool on, int base,
                                            int node, const Prim<RT>& me,
@@ -213,7 +214,7 @@ __device__ __forceinline__ void volume_dir(const L& s, double* __restrict__ x /*
   constexpr int n = N + 1, st = Stride<D, n>::value;
   constexpr int NN = Shape<DIM, N>::NN;
   constexpr int FULL = (n - 1) / 2;
-  constexpr int ROUNDS = FULL + (n % 2 == 0 ? 1 : 0);
+  constexpr int ROUNDS = FULL + (HALF && n % 2 == 0 ? 1 : 0);
   const int id = (node / st) % n;
   const int nb = base + node - id * st;
 #pragma unroll
@@ -260,6 +261,55 @@ __device__ __forceinline__ void volume_dir(const L& s, double* __restrict__ x /*
     }
     if constexpr (!WaveElem<DIM, N>::value) __syncthreads();
   }
+}
+
+// The half rounds of x and y in one full round (even n, EC volume flux).  Every node lies
+// in one x pair (i, i + n/2) and one y pair; on each 4-cycle
+// (a,b) -> (a+h,b) -> (a+h,b+h) -> (a,b+h) of these pairs (h = n/2, a, b < h) every node
+// takes the next edge, so a node whose x and y indices are on the same side of h evaluates
+// its x pair and the others their y pair: 64 of 64 lanes busy where the two half rounds
+// kept 32.  The y flux is the x flux of the states with v_x and v_y exchanged, its momentum
+// components exchanged back.
+template <int DIM, int N, typename RT, typename L>
+__device__ __forceinline__ void volume_xy_half(const L& s, double* __restrict__ x, bool on,
+                                               int base, int node, const Prim<RT>& me,
+                                               const double* sS, RT inv_gm1,
+                                               RT (&acc)[DIM + 2]) {
+  constexpr int n = N + 1, h = n / 2;
+  constexpr int NN = Shape<DIM, N>::NN;
+  static_assert(n % 2 == 0, "packed half rounds need an even number of nodes per line");
+  const int ix = node % n, iy = (node / n) % n;
+  const bool dy = (ix < h) != (iy < h);
+  const int id = dy ? iy : ix;
+  const int m = id < h ? id + h : id - h;
+  const int pn = base + node + (m - id) * (dy ? n : 1);
+  if (on) {
+    Prim<RT> a = me, q;
+    q.rho = s.rho[pn];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) q.v[k] = s.v[k][pn];
+    q.p = s.p[pn];
+    q.beta = s.beta[pn];
+    const RT q0 = q.v[0], q1 = q.v[1];
+    a.v[0] = dy ? me.v[1] : me.v[0];
+    a.v[1] = dy ? me.v[0] : me.v[1];
+    q.v[0] = dy ? q1 : q0;
+    q.v[1] = dy ? q0 : q1;
+    RT f[DIM + 2];
+    ec_flux<DIM, 0, RT>(a, q, inv_gm1, f);
+    const RT f1 = f[1], f2 = f[2];
+    f[1] = dy ? f2 : f1;
+    f[2] = dy ? f1 : f2;
+    const int D = dy ? 1 : 0;
+    const RT cme = (RT)sS[(D * TMAX + id) * TMAX + m];
+    const RT cpa = (RT)sS[(D * TMAX + m) * TMAX + id];
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v) {
+      acc[v] += cme * f[v];
+      lds_add(&x[v * NN + pn - base], (double)(cpa * f[v]));
+    }
+  }
+  if constexpr (!WaveElem<DIM, N>::value) __syncthreads();
 }
 
 // First-order FV on the LGL subcells in direction D with the fv flux (LLF or HLL):
@@ -478,10 +528,14 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     RT acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = SEED ? (RT)R[v] : RT(0);
-    volume_dir<DIM, N, 0, VOL, RT>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
-    volume_dir<DIM, N, 1, VOL, RT>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
+    // even n with the EC flux: the x and y half rounds run as one packed round
+    constexpr bool PACK = (N % 2 == 1) && (VOL == VOL_EC || VOL == VOL_SHOCKCAP);
+    volume_dir<DIM, N, 0, VOL, RT, !PACK>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
+    volume_dir<DIM, N, 1, VOL, RT, !PACK>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
+    if constexpr (PACK)
+      volume_xy_half<DIM, N, RT>(s, x, active, base, node, me, sT + TAB_S, inv_gm1, acc);
     if constexpr (DIM == 3)
-      volume_dir<DIM, N, 2, VOL, RT>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
+      volume_dir<DIM, N, 2, VOL, RT, true>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
     elem_sync<DIM, N>();   // every partner share has landed
     if (active) {
 #pragma unroll
