@@ -26,6 +26,14 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return fma(r, e, r);
 }
 
+// 1/x with one Newton step (relative error 2.2e-15 on gfx950, against 4.6e-8 for the bare
+// hardware reciprocal): enough where the reciprocal only forms z = (b - a)/(b + a), whose
+// square enters a series with weight <= 1/3 below z^2 = 1e-4, and for float32 results.
+__device__ __forceinline__ double rcp_nr1(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
 // sqrt(x) for normal x > 0: the hardware reciprocal square root, one Newton step on
 // (g, h) = (sqrt x, 1/(2 sqrt x)) and two residual corrections g += (x - g^2) h.
 __device__ __forceinline__ double sqrt_pos(double x) {
@@ -47,7 +55,7 @@ __device__ __forceinline__ double sqrt_pos(double x) {
 // (truncation below 1.2e-17), so one reciprocal of a + b serves the whole evaluation.
 __device__ __forceinline__ double ln_mean(double a, double b) {
   const double s = a + b, d = b - a;
-  const double r = rcp_nr(s);
+  const double r = rcp_nr1(s);   // only z is formed from it
   const double z = d * r, z2 = z * z;
   if (z2 < 1.0e-4)
     return 0.5 * s * (1.0 + z2 * (-1.0 / 3.0 + z2 * (-4.0 / 45.0 + z2 * (-44.0 / 945.0))));
@@ -69,7 +77,7 @@ __device__ __forceinline__ double inv_ln_mean(double a, double b) {
 // float32.
 __device__ __forceinline__ float ln_mean(float a, float b) {
   const double s = (double)a + (double)b, d = (double)b - (double)a;
-  const double r = rcp_nr(s);
+  const double r = rcp_nr1(s);
   const double z = d * r, z2 = z * z;
   if (z2 < 1.0e-4)
     return (float)(0.5 * s * (1.0 + z2 * (-1.0 / 3.0 + z2 * (-4.0 / 45.0 + z2 * (-44.0 / 945.0)))));
@@ -78,7 +86,7 @@ __device__ __forceinline__ float ln_mean(float a, float b) {
 
 __device__ __forceinline__ float inv_ln_mean(float a, float b) {
   const double s = (double)a + (double)b, d = (double)b - (double)a;
-  const double r = rcp_nr(s);
+  const double r = rcp_nr1(s);   // float32 result
   const double z = d * r, z2 = z * z;
   if (z2 < 1.0e-4)
     return (float)(2.0 * r * (1.0 + z2 * (1.0 / 3.0 + z2 * (1.0 / 5.0 + z2 * (1.0 / 7.0)))));
