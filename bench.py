@@ -107,9 +107,9 @@ def main():
     ap.add_argument("--workload", default="tgv_32")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="rhs,mixed,batched,sedov,dwave",
-                    help="comma list of extra variants: rhs, mixed, batched, sedov, dwave "
-                         "('' for none)")
+    ap.add_argument("--variants", default="rhs,mixed,batched,sedov,weak,dwave",
+                    help="comma list of extra variants: rhs, mixed, batched, sedov, weak, "
+                         "dwave ('' for none)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -190,6 +190,11 @@ def main():
             variants["shockcap_sedov_32_fp64"] = bench_sedov(args)
         except Exception as e:
             variants["shockcap_sedov_32_fp64"] = {"error": str(e)}
+    if "weak" in want:
+        try:
+            variants["weak_hll_tgv_32_fp64"] = bench_weak(args)
+        except Exception as e:
+            variants["weak_hll_tgv_32_fp64"] = {"error": str(e)}
     if "dwave" in want:
         try:
             variants["density_wave_2d_fp64"] = bench_density_wave(args)
@@ -256,6 +261,21 @@ def bench_density_wave(args):
     del torch
     return {"value": 100 * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": 100,
             "ms_per_step": secs / 100 * 1e3}
+
+
+def bench_weak(args):
+    """Weak-form DG + HLL on the 32^3 N = 3 TGV (the paper's other measured solver): full RK
+    steps, with the stage kernel's live average and its HBM fraction (same 152 B/node)."""
+    from paper_2108_06476_amd import dgx, inputs
+    cfg = dict(inputs.workload("tgv_32"), volume="weak", surface="hll")
+    s = dgx.Solver(**cfg)
+    u = make_state(s, "tgv_32")
+    steps = max(5, args.steps // 2)
+    secs, prof = time_steps(s, u, steps, 2, profile=True)
+    avg_ms = prof[0]
+    gbs = 152.0 * s.num_nodes / (avg_ms * 1e-3) / 1e9
+    return {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps,
+            "stage_us": round(avg_ms * 1e3, 2), "stage_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def kernel_source_hash():

@@ -55,6 +55,8 @@ typedef enum {
   DGX_VOL_EC = 0,          /* flux differencing, entropy-conservative two-point flux */
   DGX_VOL_CENTRAL = 1,     /* flux differencing, central flux (= weak form) */
   DGX_VOL_SHOCKCAP_HG = 2, /* blended: (1-alpha) EC flux differencing + alpha FV */
+  DGX_VOL_WEAK = 3,        /* weak form: (2/h) sum_m Dhat_im f(u_m), Dhat_im = (w_m/w_i) D_mi
+                              (Section 3.1, the paper's other measured DG solver); FP64 */
   DGX_VOL_NONE = 4         /* no volume term (testing: surface terms only) */
 } dgx_volume;
 

@@ -17,6 +17,7 @@ namespace dgx {
 // Table layout (doubles), fixed strides for polydeg <= 7 (8 nodes per direction).
 constexpr int TMAX = 8;
 constexpr int TAB_S = 0;                           // [3][8][8]  -(2/h_d) S_im, S = 2D - M^-1 B
+                                                   //            (weak form: (2/h_d) Dhat_im)
 constexpr int TAB_LIFT = TAB_S + 3 * TMAX * TMAX;  // [3][2]     +(2/h_d)/w_0, -(2/h_d)/w_N
 constexpr int TAB_FV = TAB_LIFT + 6;               // [3][8]     -(2/h_d)/w_i
 constexpr int TAB_VINV = TAB_FV + 3 * TMAX;        // [8][8]     orthonormal-Legendre V^-1
@@ -25,7 +26,7 @@ constexpr int TAB_X = TAB_W + TMAX;                // [8]        LGL nodes
 constexpr int TAB_JAC = TAB_X + TMAX;              // [3]        2/h_d
 constexpr int TAB_SIZE = TAB_JAC + 3;
 
-enum { VOL_EC = 0, VOL_CENTRAL = 1, VOL_SHOCKCAP = 2, VOL_NONE = 4 };
+enum { VOL_EC = 0, VOL_CENTRAL = 1, VOL_SHOCKCAP = 2, VOL_WEAK = 3, VOL_NONE = 4 };
 enum { EPI_RHS = 0, EPI_RK = 1 };
 
 // Element tiles: NE elements of NN nodes per block of up to BUDGET threads.
@@ -438,11 +439,41 @@ struct StageArgs {
   int fvf;               // subcell FV flux (SURF_LLF or SURF_HLL)
 };
 
+// Weak form: the physical fluxes f^d_v of every node, contracted along the lines.
+template <int DIM, int NE_NN, int XB>
+struct WeakLds {
+  double f[DIM][DIM + 2][NE_NN];
+  alignas(16) unsigned char xb[XB];   // per element: wave speeds (elements of several waves)
+};
+
 template <int DIM, int N, int VOL, typename RT, int BUDGET = 256>
 struct StageLdsOf {
   using SS = StageShape<DIM, N, RT, BUDGET>;
   using type = StageLds<RT, DIM, SS::NENN, SS::XB, (VOL == VOL_CENTRAL || VOL == VOL_SHOCKCAP)>;
 };
+
+template <int DIM, int N, typename RT, int BUDGET>
+struct StageLdsOf<DIM, N, VOL_WEAK, RT, BUDGET> {
+  using SS = StageShape<DIM, N, RT, BUDGET>;
+  // one-wave elements reduce their wave speeds with DPP moves: no scratch slot
+  using type = WeakLds<DIM, SS::NENN, WaveElem<DIM, N>::value ? 16 : SS::XB>;
+};
+
+// Weak-form volume term along direction D: R_v += sum_m (2/h_D) Dhat_{i m} f^D_v(u_m) over
+// the line of the node (i = its index along D), fluxes read from LDS.
+template <int DIM, int N, int D, typename L>
+__device__ __forceinline__ void weak_dir(const L& s, int base, int node, const double* sD,
+                                         double (&R)[DIM + 2]) {
+  constexpr int n = N + 1, st = Stride<D, n>::value;
+  const int id = (node / st) % n;
+  const int nb = base + node - id * st;
+#pragma unroll
+  for (int m = 0; m < n; ++m) {
+    const double c = sD[(D * TMAX + id) * TMAX + m];
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v) R[v] = fma(c, s.f[D][v][nb + m * st], R[v]);
+  }
+}
 
 // One tile of elements (the body of the stage kernels).  sT holds the run's operator
 // tables in LDS; they are loaded by the caller and become visible at the first barrier.
@@ -478,15 +509,30 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     }
     if (!cons_to_prim<DIM>(um, g.gamma, qd)) *g.flag = 1;
     const int li = base + node;
-    if constexpr (CONS) s.c[li] = qd.c;
-    s.rho[li] = (RT)qd.rho;
+    if constexpr (VOL == VOL_WEAK) {   // physical fluxes of this node
+      double f[NV];
+      phys_flux<DIM, 0>(um, qd, f);
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) s.v[k][li] = (RT)qd.v[k];
-    s.p[li] = (RT)qd.p;
-    s.beta[li] = (RT)qd.beta;
-    if constexpr (CONS) {
+      for (int v = 0; v < NV; ++v) s.f[0][v][li] = f[v];
+      phys_flux<DIM, 1>(um, qd, f);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) s.u[v][li] = um[v];
+      for (int v = 0; v < NV; ++v) s.f[1][v][li] = f[v];
+      if constexpr (DIM == 3) {
+        phys_flux<DIM, 2>(um, qd, f);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s.f[2][v][li] = f[v];
+      }
+    } else {
+      if constexpr (CONS) s.c[li] = qd.c;
+      s.rho[li] = (RT)qd.rho;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) s.v[k][li] = (RT)qd.v[k];
+      s.p[li] = (RT)qd.p;
+      s.beta[li] = (RT)qd.beta;
+      if constexpr (CONS) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) s.u[v][li] = um[v];
+      }
     }
   } else {
 #pragma unroll
@@ -495,7 +541,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     qd.v[0] = qd.v[1] = qd.v[2] = 0.0;
   }
 
-  if (inb) {   // zero this node's partner-share accumulator
+  if (VOL != VOL_WEAK && inb) {   // zero this node's partner-share accumulator
     double* x = reinterpret_cast<double*>(s.xb + le * SS::SLOT);
 #pragma unroll
     for (int v = 0; v < NV; ++v) x[v * NN + node] = 0.0;
@@ -513,7 +559,13 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   }
 
   // ---- volume
-  if constexpr (VOL != VOL_NONE) {
+  if constexpr (VOL == VOL_WEAK) {
+    if (active) {
+      weak_dir<DIM, N, 0>(s, base, node, sT + TAB_S, R);
+      weak_dir<DIM, N, 1>(s, base, node, sT + TAB_S, R);
+      if constexpr (DIM == 3) weak_dir<DIM, N, 2>(s, base, node, sT + TAB_S, R);
+    }
+  } else if constexpr (VOL != VOL_NONE) {
     double* x = reinterpret_cast<double*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);
     Prim<RT> me;
     me.rho = (RT)qd.rho;

@@ -54,6 +54,7 @@ struct Launch {
     if (vol == VOL_CENTRAL) return stage1<VOL_CENTRAL, EPI, double>(st, a, g);
     if (vol == VOL_NONE) return stage1<VOL_NONE, EPI, double>(st, a, g);
     if (vol == VOL_SHOCKCAP) return stage1<VOL_SHOCKCAP, EPI, double>(st, a, g);
+    if (vol == VOL_WEAK) return stage1<VOL_WEAK, EPI, double>(st, a, g);
     return hipErrorInvalidValue;
   }
 

@@ -79,7 +79,7 @@ bool lgl_tables(int N, double* x, double* w, double* D, double* Vinv) {
   return true;
 }
 
-bool stage_tables(int N, const double* h, double* T) {
+bool stage_tables(int N, const double* h, double* T, bool weak) {
   double x[16], w[16], D[256], Vinv[256];
   if (N < 1 || N >= TMAX || !lgl_tables(N, x, w, D, Vinv)) return false;
   const int n = N + 1;
@@ -87,7 +87,8 @@ bool stage_tables(int N, const double* h, double* T) {
     const double jac = 2.0 / h[d];
     for (int i = 0; i < n; ++i)
       for (int m = 0; m < n; ++m)
-        T[TAB_S + (d * TMAX + i) * TMAX + m] = (i == m) ? 0.0 : -jac * 2.0 * D[i * n + m];
+        T[TAB_S + (d * TMAX + i) * TMAX + m] =
+            weak ? jac * (w[m] / w[i]) * D[m * n + i] : ((i == m) ? 0.0 : -jac * 2.0 * D[i * n + m]);
     T[TAB_LIFT + d * 2 + 0] = jac / w[0];
     T[TAB_LIFT + d * 2 + 1] = -jac / w[N];
     for (int i = 0; i < n; ++i) T[TAB_FV + d * TMAX + i] = -jac / w[i];

@@ -9,7 +9,9 @@ bool lgl_tables(int N, double* x, double* w, double* D, double* Vinv);
 
 // The per-handle operator tables of the kernels (layout TAB_* in kernels.h) for polydeg N
 // and cell sizes h[3]: -(2/h_d) S with S = 2D - M^-1 B, lift factors +-(2/h_d)/w,
-// FV factors -(2/h_d)/w_i, Legendre V^-1, LGL weights and nodes, 2/h_d.
-bool stage_tables(int N, const double* h, double* T /* TAB_SIZE doubles, zeroed */);
+// FV factors -(2/h_d)/w_i, Legendre V^-1, LGL weights and nodes, 2/h_d.  For the weak form
+// the first block holds (2/h_d) Dhat instead, Dhat_im = (w_m/w_i) D_mi.
+bool stage_tables(int N, const double* h, double* T /* TAB_SIZE doubles, zeroed */,
+                  bool weak = false);
 
 }  // namespace dgx
