@@ -191,10 +191,11 @@ def main():
         except Exception as e:
             variants["shockcap_sedov_32_fp64"] = {"error": str(e)}
     if "weak" in want:
-        try:
-            variants["weak_hll_tgv_32_fp64"] = bench_weak(args)
-        except Exception as e:
-            variants["weak_hll_tgv_32_fp64"] = {"error": str(e)}
+        for vol in ("weak", "weak_mfma"):
+            try:
+                variants[f"{vol}_hll_tgv_32_fp64"] = bench_weak(args, vol)
+            except Exception as e:
+                variants[f"{vol}_hll_tgv_32_fp64"] = {"error": str(e)}
     if "dwave" in want:
         try:
             variants["density_wave_2d_fp64"] = bench_density_wave(args)
@@ -263,11 +264,12 @@ def bench_density_wave(args):
             "ms_per_step": secs / 100 * 1e3}
 
 
-def bench_weak(args):
-    """Weak-form DG + HLL on the 32^3 N = 3 TGV (the paper's other measured solver): full RK
+def bench_weak(args, volume="weak"):
+    """Weak-form DG + HLL on the 32^3 N = 3 TGV (the paper's other measured solver), with the
+    line contractions on the VALU ("weak") or on the matrix cores ("weak_mfma"): full RK
     steps, with the stage kernel's live average and its HBM fraction (same 152 B/node)."""
     from paper_2108_06476_amd import dgx, inputs
-    cfg = dict(inputs.workload("tgv_32"), volume="weak", surface="hll")
+    cfg = dict(inputs.workload("tgv_32"), volume=volume, surface="hll")
     s = dgx.Solver(**cfg)
     u = make_state(s, "tgv_32")
     steps = max(5, args.steps // 2)

@@ -57,7 +57,10 @@ typedef enum {
   DGX_VOL_SHOCKCAP_HG = 2, /* blended: (1-alpha) EC flux differencing + alpha FV */
   DGX_VOL_WEAK = 3,        /* weak form: (2/h) sum_m Dhat_im f(u_m), Dhat_im = (w_m/w_i) D_mi
                               (Section 3.1, the paper's other measured DG solver); FP64 */
-  DGX_VOL_NONE = 4         /* no volume term (testing: surface terms only) */
+  DGX_VOL_NONE = 4,        /* no volume term (testing: surface terms only) */
+  DGX_VOL_WEAK_MFMA = 5    /* the weak form with its line contractions on the matrix cores
+                              (v_mfma_f64_4x4x4f64); 3D, polydeg 3 only, else
+                              DGX_EUNSUPPORTED */
 } dgx_volume;
 
 typedef enum {

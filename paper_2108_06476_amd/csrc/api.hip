@@ -274,8 +274,9 @@ dgx_status dgx_create(const dgx_config* cfg, void* hip_stream, dgx_handle* out) 
     if (c.cells[d] < 1 || !(c.xmax[d] > c.xmin[d])) return DGX_EINVAL;
   if (c.dim == 2 && c.cells[2] != 1) return DGX_EINVAL;
   if (c.volume != DGX_VOL_EC && c.volume != DGX_VOL_CENTRAL && c.volume != DGX_VOL_SHOCKCAP_HG &&
-      c.volume != DGX_VOL_WEAK && c.volume != DGX_VOL_NONE)
+      c.volume != DGX_VOL_WEAK && c.volume != DGX_VOL_NONE && c.volume != DGX_VOL_WEAK_MFMA)
     return DGX_EINVAL;
+  if (c.volume == DGX_VOL_WEAK_MFMA && (c.dim != 3 || c.polydeg != 3)) return DGX_EUNSUPPORTED;
   if (c.surface < DGX_SURF_LLF || c.surface > DGX_SURF_NONE) return DGX_EINVAL;
   if (c.volume == DGX_VOL_SHOCKCAP_HG) {
     if (c.fv_flux != DGX_SURF_LLF && c.fv_flux != DGX_SURF_HLL) return DGX_EINVAL;
@@ -310,7 +311,8 @@ dgx_status dgx_create(const dgx_config* cfg, void* hip_stream, dgx_handle* out) 
 
   // operator tables
   std::vector<double> T(TAB_SIZE, 0.0);
-  if (!stage_tables(h->N, h->h, T.data(), c.volume == DGX_VOL_WEAK)) {
+  if (!stage_tables(h->N, h->h, T.data(),
+                    c.volume == DGX_VOL_WEAK || c.volume == DGX_VOL_WEAK_MFMA)) {
     delete h;
     return DGX_EINVAL;
   }

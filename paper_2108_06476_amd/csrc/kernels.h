@@ -26,7 +26,8 @@ constexpr int TAB_X = TAB_W + TMAX;                // [8]        LGL nodes
 constexpr int TAB_JAC = TAB_X + TMAX;              // [3]        2/h_d
 constexpr int TAB_SIZE = TAB_JAC + 3;
 
-enum { VOL_EC = 0, VOL_CENTRAL = 1, VOL_SHOCKCAP = 2, VOL_WEAK = 3, VOL_NONE = 4 };
+enum { VOL_EC = 0, VOL_CENTRAL = 1, VOL_SHOCKCAP = 2, VOL_WEAK = 3, VOL_NONE = 4,
+       VOL_WEAK_MFMA = 5 };
 enum { EPI_RHS = 0, EPI_RK = 1 };
 
 // Element tiles: NE elements of NN nodes per block of up to BUDGET threads.
@@ -459,6 +460,48 @@ struct StageLdsOf<DIM, N, VOL_WEAK, RT, BUDGET> {
   using type = WeakLds<DIM, SS::NENN, WaveElem<DIM, N>::value ? 16 : SS::XB>;
 };
 
+template <int DIM, int N, typename RT, int BUDGET>
+struct StageLdsOf<DIM, N, VOL_WEAK_MFMA, RT, BUDGET> {
+  using type = typename StageLdsOf<DIM, N, VOL_WEAK, RT, BUDGET>::type;
+};
+
+// A double from lane `src` of the wave (ds_bpermute on both halves).
+__device__ __forceinline__ double lane_read_f64(double x, int src) {
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(x));
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+// Weak-form volume term of a 3D N = 3 element (one wave, lane = node = ix + 4 iy + 16 iz) on
+// the matrix cores: v_mfma_f64_4x4x4f64 multiplies four 4x4 blocks per instruction; with
+// (bits 0-1, 2-3, 4-5) of the lane holding (row, block, k) of A, (column, block, k) of B and
+// (column, block, row) of the result, one instruction contracts all 16 lines of one variable
+// in one direction:
+//   z: A = Dhat_z[a][c], B = the lane's own flux: result on the owner lane;
+//   x: A = flux of node (c, b, a) (gathered from LDS), B = Dhat_x[a][c] (the transposed
+//      product): result on the owner lane;
+//   y: A = Dhat_y[a][c], B = flux of node (a, c, b): the result for node (a, c, b) sits on
+//      lane (a, b, c); the swap of the two upper bit pairs is its own inverse, so each lane
+//      reads its value from lane (a, c, b).
+// (a, b, c) = (l & 3, (l >> 2) & 3, l >> 4).  The running sum R is the accumulator input.
+template <typename L>
+__device__ __forceinline__ void weak_mfma_n3(const L& s, int base, int l, const double* sD,
+                                             double (&R)[5]) {
+  const int a = l & 3, b = (l >> 2) & 3, c = l >> 4;
+  const double dx = sD[(0 * TMAX + a) * TMAX + c];
+  const double dy = sD[(1 * TMAX + a) * TMAX + c];
+  const double dz = sD[(2 * TMAX + a) * TMAX + c];
+  const int nx = c + 4 * b + 16 * a;
+  const int ny = a + 4 * c + 16 * b;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    double r = __builtin_amdgcn_mfma_f64_4x4x4f64(dz, s.f[2][v][base + l], R[v], 0, 0, 0);
+    r = __builtin_amdgcn_mfma_f64_4x4x4f64(s.f[0][v][base + nx], dx, r, 0, 0, 0);
+    const double oy = __builtin_amdgcn_mfma_f64_4x4x4f64(dy, s.f[1][v][base + ny], 0.0, 0, 0, 0);
+    R[v] = r + lane_read_f64(oy, ny);
+  }
+}
+
 // Weak-form volume term along direction D: R_v += sum_m (2/h_D) Dhat_{i m} f^D_v(u_m) over
 // the line of the node (i = its index along D), fluxes read from LDS.
 template <int DIM, int N, int D, typename L>
@@ -509,7 +552,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     }
     if (!cons_to_prim<DIM>(um, g.gamma, qd)) *g.flag = 1;
     const int li = base + node;
-    if constexpr (VOL == VOL_WEAK) {   // physical fluxes of this node
+    if constexpr (VOL == VOL_WEAK || VOL == VOL_WEAK_MFMA) {   // physical fluxes of this node
       double f[NV];
       phys_flux<DIM, 0>(um, qd, f);
 #pragma unroll
@@ -541,7 +584,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     qd.v[0] = qd.v[1] = qd.v[2] = 0.0;
   }
 
-  if (VOL != VOL_WEAK && inb) {   // zero this node's partner-share accumulator
+  if (VOL != VOL_WEAK && VOL != VOL_WEAK_MFMA && inb) {   // zero the partner-share accumulator
     double* x = reinterpret_cast<double*>(s.xb + le * SS::SLOT);
 #pragma unroll
     for (int v = 0; v < NV; ++v) x[v * NN + node] = 0.0;
@@ -559,7 +602,10 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   }
 
   // ---- volume
-  if constexpr (VOL == VOL_WEAK) {
+  if constexpr (VOL == VOL_WEAK_MFMA) {
+    static_assert(DIM == 3 && N == 3, "the matrix-core weak form is built for 3D, N = 3");
+    if (active) weak_mfma_n3(s, base, node, sT + TAB_S, R);   // uniform: one element per wave
+  } else if constexpr (VOL == VOL_WEAK) {
     if (active) {
       weak_dir<DIM, N, 0>(s, base, node, sT + TAB_S, R);
       weak_dir<DIM, N, 1>(s, base, node, sT + TAB_S, R);
@@ -690,8 +736,11 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   }
 }
 
+// The matrix-core variant asks for 4 waves per SIMD (its accumulators would otherwise push
+// the register count past 128).
 template <int DIM, int N, int VOL, int EPI, typename RT>
-__global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_stage(StageArgs a, Geom g) {
+__global__ __launch_bounds__((Shape<DIM, N>::THREADS), (VOL == VOL_WEAK_MFMA ? 4 : 1))
+void k_stage(StageArgs a, Geom g) {
   __shared__ typename StageLdsOf<DIM, N, VOL, RT>::type s;
   __shared__ double sT[TAB_SIZE];
   for (int i = threadIdx.x; i < TAB_SIZE; i += blockDim.x) sT[i] = g.tab[i];

@@ -55,6 +55,10 @@ struct Launch {
     if (vol == VOL_NONE) return stage1<VOL_NONE, EPI, double>(st, a, g);
     if (vol == VOL_SHOCKCAP) return stage1<VOL_SHOCKCAP, EPI, double>(st, a, g);
     if (vol == VOL_WEAK) return stage1<VOL_WEAK, EPI, double>(st, a, g);
+    if (vol == VOL_WEAK_MFMA) {
+      if constexpr (DIM == 3 && N == 3) return stage1<VOL_WEAK_MFMA, EPI, double>(st, a, g);
+      return hipErrorInvalidValue;
+    }
     return hipErrorInvalidValue;
   }
 

@@ -13,7 +13,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdgx.so")
 
-VOLUME = {"ec": 0, "central": 1, "shockcap_hg": 2, "weak": 3, "none": 4}
+VOLUME = {"ec": 0, "central": 1, "shockcap_hg": 2, "weak": 3, "none": 4, "weak_mfma": 5}
 SURFACE = {"llf": 0, "hll": 1, "ec": 2, "none": 3}
 PRECISION = {"fp64": 0, "mixed": 1}
 STATUS = {0: "DGX_OK", 1: "DGX_EINVAL", 2: "DGX_EHIP", 3: "DGX_ENOMEM", 4: "DGX_ENONPHYS",

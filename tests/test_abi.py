@@ -47,6 +47,12 @@ def test_unsupported_config_reported():
     cfg = dgx.make_config(3, 3, (2, 2, 2), (0, 0, 0), (1, 1, 1), volume="central",
                           precision="mixed")
     assert L.dgx_create(C.byref(cfg), None, C.byref(h)) == 5
+    for dim, N in [(3, 4), (2, 3)]:                                   # matrix-core weak form
+        cells = (2, 2, 2) if dim == 3 else (2, 2, 1)
+        cfg = dgx.make_config(dim, N, cells, (0, 0, 0), (1, 1, 1), volume="weak_mfma")
+        assert L.dgx_create(C.byref(cfg), None, C.byref(h)) == 5
+    cfg = dgx.make_config(3, 3, (2, 2, 2), (0, 0, 0), (1, 1, 1), volume="weak", precision="mixed")
+    assert L.dgx_create(C.byref(cfg), None, C.byref(h)) == 5
 
 
 def test_null_handle_calls_fail_cleanly():

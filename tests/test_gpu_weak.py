@@ -109,3 +109,52 @@ def test_weak_steps_against_oracle():
 def test_weak_rejects_mixed_precision():
     with pytest.raises(dgx.DgxError):
         dgx.Solver(**dict(_cfg(3, 3, 2), precision="mixed"))
+
+
+# --------------------------------------------------------------------------- matrix cores
+@pytest.mark.parametrize("surf", ["hll", "llf", "ec", "none"])
+@pytest.mark.parametrize("kind", ["nodal", "smooth"])
+@pytest.mark.parametrize("cells", [(3, 3, 2), (1, 2, 3), (5, 1, 1)])
+def test_weak_mfma_rhs_parity(surf, kind, cells):
+    cfg = _cfg(3, 3, cells, surf, volume="weak_mfma")
+    print("case", cfg, kind, flush=True)
+    o = oracle.Oracle(**dict(cfg, volume="weak"))
+    s = dgx.Solver(**cfg)
+    u = _state(o, kind, 300 + cells[0])
+    ref = o.rhs(u)
+    got = host(s.rhs(dev(u)))
+    e = err_v(got, ref, u, 3, _h(cfg))
+    print("  err_v", e, flush=True)
+    assert np.all(e <= TOL_FP64), e
+
+
+def test_weak_mfma_full_tgv_32_and_steps():
+    cfg = dict(inputs.workload("tgv_32"), volume="weak_mfma", surface="hll")
+    o = oracle.Oracle(**dict(cfg, volume="weak"))
+    s = dgx.Solver(**cfg)
+    u = inputs.tgv(o.node_coords())
+    e = err_v(host(s.rhs(dev(u))), o.rhs(u), u, 3, 2 * np.pi / 32)
+    print("weak_mfma tgv_32 err_v", e, flush=True)
+    assert np.all(e <= TOL_FP64), e
+    small = dict(inputs.scaled(inputs.workload("tgv_32"), cells=(6, 5, 4)), volume="weak_mfma",
+                 surface="hll")
+    o2 = oracle.Oracle(**dict(small, volume="weak"))
+    s2 = dgx.Solver(**small)
+    u0 = inputs.tgv(o2.node_coords())
+    ref, _ = o2.step(u0, 20, cfl=0.5)
+    ud = dev(u0)
+    s2.step(ud, 20, cfl=0.5)
+    d = np.abs(host(ud) - ref).max() / np.abs(ref).max()
+    print("weak_mfma 20 steps: max|du|/max|u|", d, flush=True)
+    assert d <= 1e-12
+
+
+def test_weak_mfma_matches_valu_weak():
+    c = _cfg(3, 3, (4, 3, 2), "llf")
+    o = oracle.Oracle(**dict(c, volume="weak"))
+    u = _state(o, "smooth", 77)
+    r1 = host(dgx.Solver(**c).rhs(dev(u)))
+    r2 = host(dgx.Solver(**dict(c, volume="weak_mfma")).rhs(dev(u)))
+    e = err_v(r2, r1, u, 3, _h(c))
+    print("mfma vs valu weak err_v", e, flush=True)
+    assert np.all(e <= TOL_FP64), e
