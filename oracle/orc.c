@@ -770,3 +770,431 @@ int orc_num_threads(void)
   return 1;
 #endif
 }
+
+/* ========================================================================= */
+/* Curvilinear hexahedral mesh (Section 3.1): the periodic box [-1,1]^3 with   */
+/* K^3 elements, warped by the mapping of Eq. (2); a manufactured solution of  */
+/* the Euler equations with its source term (the PID study's Euler problem;    */
+/* the paper names it without printing it, the one below is this oracle's      */
+/* reading).                                                                   */
+/* ========================================================================= */
+
+/* Eq. (2): y first, then x (uses y), then z (uses x and y); a = warp amplitude. */
+int orc_curv_map(double a, const double *xi, double *X)
+{
+  const double pi = 3.14159265358979323846;
+  const double s = xi[0], e = xi[1], z = xi[2];
+  const double y = e + a * (cos(1.5 * pi * s) * cos(0.5 * pi * e) * cos(0.5 * pi * z));
+  const double x = s + a * (cos(0.5 * pi * s) * cos(2.0 * pi * y) * cos(0.5 * pi * z));
+  const double w = z + a * (cos(0.5 * pi * x) * cos(pi * y) * cos(0.5 * pi * z));
+  X[0] = x;
+  X[1] = y;
+  X[2] = w;
+  return ORC_OK;
+}
+
+/* Manufactured solution (reading): rho = 2 + A sin(theta), theta = k (x + y + z) - om t,
+ * v = (1, 1, 1), rho E = rho^2, with A = 0.1, k = pi, om = 2 pi; p = (gamma-1)(rho^2 - 1.5 rho).
+ * Its source s = du/dt + div f(u), derived by hand (h = A cos theta):
+ *   s_rho   = (3k - om) h
+ *   s_rhov  = (3k - om) h + (gamma-1)(2 rho - 1.5) k h      (each component)
+ *   s_rhoE  = -2 rho om h + 3 k (2 rho + (gamma-1)(2 rho - 1.5)) h                          */
+int orc_curv_mms(double gamma, const double *x, double t, double *u, double *s)
+{
+  const double pi = 3.14159265358979323846;
+  const double A = 0.1, k = pi, om = 2.0 * pi;
+  const double th = k * (x[0] + x[1] + x[2]) - om * t;
+  const double rho = 2.0 + A * sin(th);
+  const double h = A * cos(th);
+  if (u) {
+    u[0] = rho;
+    u[1] = rho;
+    u[2] = rho;
+    u[3] = rho;
+    u[4] = rho * rho;
+  }
+  if (s) {
+    const double dp = (gamma - 1.0) * (2.0 * rho - 1.5) * k * h;
+    s[0] = (3.0 * k - om) * h;
+    s[1] = s[0] + dp;
+    s[2] = s[0] + dp;
+    s[3] = s[0] + dp;
+    s[4] = -2.0 * rho * om * h + 3.0 * k * (2.0 * rho + (gamma - 1.0) * (2.0 * rho - 1.5)) * h;
+  }
+  return ORC_OK;
+}
+
+typedef struct {
+  mesh_t m;           /* 3D, n, S, w, D of the reference element; h unused */
+  int K;
+  double warp;
+  double *xyz;        /* [3][E][NN] */
+  double *Ja;         /* [3 (reference direction i)][3 (component n)][E][NN]: (J a^i)_n */
+  double *J;          /* [E][NN] */
+} curv_t;
+
+static int curv_setup(const orc_curv_config *cfg, curv_t *c)
+{
+  if (!cfg || cfg->cells < 1 || cfg->polydeg < 1 || cfg->polydeg > ORC_MAXN) return ORC_EINVAL;
+  if (!(cfg->gamma > 1.0)) return ORC_EINVAL;
+  if (cfg->volume != ORC_VOL_EC && cfg->volume != ORC_VOL_CENTRAL && cfg->volume != ORC_VOL_NONE)
+    return ORC_EINVAL;
+  orc_config q;
+  memset(&q, 0, sizeof(q));
+  q.dim = 3;
+  q.polydeg = cfg->polydeg;
+  for (int d = 0; d < 3; ++d) {
+    q.cells[d] = cfg->cells;
+    q.xmin[d] = -1.0;
+    q.xmax[d] = 1.0;
+  }
+  q.gamma = cfg->gamma;
+  int st = setup(&q, &c->m);
+  if (st) return st;
+  c->K = cfg->cells;
+  c->warp = cfg->warp;
+  const int64_t len = c->m.E * c->m.NN;
+  c->xyz = malloc(sizeof(double) * 3 * len);
+  c->Ja = malloc(sizeof(double) * 9 * len);
+  c->J = malloc(sizeof(double) * len);
+  if (!c->xyz || !c->Ja || !c->J) return ORC_EINVAL;
+  const mesh_t *m = &c->m;
+  const int n = m->n, NN = m->NN;
+  const double hr = 2.0 / c->K;   /* element width in the reference box */
+#pragma omp parallel for schedule(static)
+  for (int64_t e = 0; e < m->E; ++e) {
+    int ec[3];
+    elem_coords(m, e, ec);
+    double X[3][NMAX * NMAX * NMAX], dX[3][3][NMAX * NMAX * NMAX], V[3][NMAX * NMAX * NMAX];
+    /* node positions: the mapping of the reference-box point of each LGL node */
+    for (int node = 0; node < NN; ++node) {
+      int idx[3];
+      node_idx(m, node, idx);
+      double xi[3], P[3];
+      for (int d = 0; d < 3; ++d) xi[d] = -1.0 + hr * (ec[d] + 0.5 * (1.0 + m->x[idx[d]]));
+      orc_curv_map(c->warp, xi, P);
+      for (int d = 0; d < 3; ++d) X[d][node] = P[d];
+    }
+    /* dX[j][comp][node] = derivative of the interpolant of X_comp along element direction j */
+    for (int j = 0; j < 3; ++j)
+      for (int comp = 0; comp < 3; ++comp)
+        for (int node = 0; node < NN; ++node) {
+          int idx[3], pidx[3];
+          node_idx(m, node, idx);
+          double sum = 0.0;
+          for (int mm = 0; mm < n; ++mm) {
+            pidx[0] = idx[0]; pidx[1] = idx[1]; pidx[2] = idx[2];
+            pidx[j] = mm;
+            sum = sum + m->D[idx[j] * n + mm] * X[comp][node_of(m, pidx)];
+          }
+          dX[j][comp][node] = sum;
+        }
+    for (int node = 0; node < NN; ++node) {
+      double c0 = dX[1][1][node] * dX[2][2][node] - dX[1][2][node] * dX[2][1][node];
+      double c1 = dX[1][2][node] * dX[2][0][node] - dX[1][0][node] * dX[2][2][node];
+      double c2 = dX[1][0][node] * dX[2][1][node] - dX[1][1][node] * dX[2][0][node];
+      c->J[e * NN + node] = dX[0][0][node] * c0 + dX[0][1][node] * c1 + dX[0][2][node] * c2;
+    }
+    /* conservative curl form: (J a^i)_nc = -[curl_s (X_l grad_s X_m)]_i, (nc, m, l) cyclic */
+    for (int nc = 0; nc < 3; ++nc) {
+      const int mm_ = (nc + 1) % 3, l = (nc + 2) % 3;
+      for (int j = 0; j < 3; ++j)
+        for (int node = 0; node < NN; ++node) V[j][node] = X[l][node] * dX[j][mm_][node];
+      for (int node = 0; node < NN; ++node) {
+        int idx[3];
+        node_idx(m, node, idx);
+        /* dV[j][k] = derivative of V_k along direction j at this node */
+        double dV[3][3];
+        for (int j = 0; j < 3; ++j)
+          for (int k = 0; k < 3; ++k) {
+            double sum = 0.0;
+            for (int q2 = 0; q2 < n; ++q2) {
+              int pidx[3] = {idx[0], idx[1], idx[2]};
+              pidx[j] = q2;
+              sum = sum + m->D[idx[j] * n + q2] * V[k][node_of(m, pidx)];
+            }
+            dV[j][k] = sum;
+          }
+        const double curl[3] = {dV[1][2] - dV[2][1], dV[2][0] - dV[0][2], dV[0][1] - dV[1][0]};
+        for (int i = 0; i < 3; ++i) c->Ja[((int64_t)(i * 3 + nc) * m->E + e) * NN + node] = -curl[i];
+      }
+    }
+    for (int d = 0; d < 3; ++d)
+      for (int node = 0; node < NN; ++node) c->xyz[((int64_t)d * m->E + e) * NN + node] = X[d][node];
+  }
+  return ORC_OK;
+}
+
+static void curv_free(curv_t *c)
+{
+  free(c->xyz);
+  free(c->Ja);
+  free(c->J);
+}
+
+int64_t orc_curv_num_nodes(const orc_curv_config *cfg)
+{
+  if (!cfg || cfg->cells < 1 || cfg->polydeg < 1 || cfg->polydeg > ORC_MAXN) return -1;
+  const int64_t n = cfg->polydeg + 1;
+  return (int64_t)cfg->cells * cfg->cells * cfg->cells * n * n * n;
+}
+
+int orc_curv_geometry(const orc_curv_config *cfg, double *xyz, double *Ja, double *J)
+{
+  curv_t c;
+  memset(&c, 0, sizeof(c));
+  int st = curv_setup(cfg, &c);
+  if (st == ORC_OK) {
+    const int64_t len = c.m.E * c.m.NN;
+    if (xyz) memcpy(xyz, c.xyz, sizeof(double) * 3 * len);
+    if (Ja) memcpy(Ja, c.Ja, sizeof(double) * 9 * len);
+    if (J) memcpy(J, c.J, sizeof(double) * len);
+  }
+  curv_free(&c);
+  return st;
+}
+
+/* Physical flux along a (not necessarily unit) vector nv: sum_k nv_k f^k(u). */
+static void flux_along(const double *u, const prim_t *q, const double *nv, double *f)
+{
+  double fk[5];
+  for (int v = 0; v < 5; ++v) f[v] = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    phys_flux(u, q, k, 3, fk);
+    for (int v = 0; v < 5; ++v) f[v] = f[v] + nv[k] * fk[v];
+  }
+}
+
+/* Two-point volume flux contracted with the averaged metric vector a:
+ * sum_n a_n f#_n(L, R) (EC or central f#). */
+static void vol_flux_curv(int vol, const double *uL, const prim_t *L, const double *uR,
+                          const prim_t *R, const double *a, double gamma, double *f)
+{
+  double fn[5];
+  for (int v = 0; v < 5; ++v) f[v] = 0.0;
+  for (int nc = 0; nc < 3; ++nc) {
+    if (vol == ORC_VOL_CENTRAL) central_flux(uL, L, uR, R, nc, 3, fn);
+    else ec_flux(L, R, nc, 3, gamma, fn);
+    for (int v = 0; v < 5; ++v) f[v] = f[v] + a[nc] * fn[v];
+  }
+}
+
+/* Interface flux through a face whose contravariant vector is nv (pointing from L to R):
+ * |nv| f*(uL, uR; nv/|nv|) for LLF and HLL (the Cartesian formulas with v_d -> v.n),
+ * sum_n nv_n f#_n(L, R) for the EC flux. */
+static void surf_flux_curv(int kind, const double *uL, const prim_t *L, const double *uR,
+                           const prim_t *R, const double *nv, double gamma, double *f)
+{
+  if (kind == ORC_SURF_EC) {
+    vol_flux_curv(ORC_VOL_EC, uL, L, uR, R, nv, gamma, f);
+    return;
+  }
+  const double len = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+  const double nh[3] = {nv[0] / len, nv[1] / len, nv[2] / len};
+  double fL[5], fR[5];
+  flux_along(uL, L, nh, fL);
+  flux_along(uR, R, nh, fR);
+  const double vnL = L->v[0] * nh[0] + L->v[1] * nh[1] + L->v[2] * nh[2];
+  const double vnR = R->v[0] * nh[0] + R->v[1] * nh[1] + R->v[2] * nh[2];
+  if (kind == ORC_SURF_LLF) {
+    double lL = fabs(vnL) + L->c, lR = fabs(vnR) + R->c;
+    double lam = lL > lR ? lL : lR;
+    for (int v = 0; v < 5; ++v) f[v] = len * (0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]));
+  } else {
+    double a = vnL - L->c, b = vnR - R->c;
+    double sL = a < b ? a : b;
+    a = vnL + L->c; b = vnR + R->c;
+    double sR = a > b ? a : b;
+    for (int v = 0; v < 5; ++v) {
+      double g;
+      if (sL >= 0.0) g = fL[v];
+      else if (sR <= 0.0) g = fR[v];
+      else g = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) / (sR - sL);
+      f[v] = len * g;
+    }
+  }
+}
+
+static void curv_ja(const curv_t *c, int i, int64_t e, int node, double *a)
+{
+  for (int nc = 0; nc < 3; ++nc) a[nc] = c->Ja[((int64_t)(i * 3 + nc) * c->m.E + e) * c->m.NN + node];
+}
+
+/* du = -(1/J) sum_i [ sum_{m != i_i} S_{i_i m} f~#_i(u_node, u_m)
+ *                     + ([i_i == N] F~*_{i+} - [i_i == 0] F~*_{i-}) / w_0 ]  + s(x, t)
+ * with f~#_i(A, B) = sum_n (Ja^i_n(A) + Ja^i_n(B))/2 f#_n(A, B), F~* the interface flux
+ * through the face's contravariant vector Ja^i (the same on both sides of the face). */
+static int curv_rhs_core(const orc_curv_config *cfg, const curv_t *c, const double *u, double t,
+                         double *du)
+{
+  const mesh_t *m = &c->m;
+  const int n = m->n, N = m->N, NN = m->NN;
+  const double gamma = cfg->gamma;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int64_t e = 0; e < m->E; ++e) {
+    double ue[NMAX * NMAX * NMAX][5];
+    prim_t qe[NMAX * NMAX * NMAX];
+    for (int node = 0; node < NN; ++node) {
+      load_node(m, u, e, node, ue[node]);
+      bad |= to_prim(ue[node], 3, gamma, &qe[node]);
+    }
+    for (int node = 0; node < NN; ++node) {
+      int idx[3];
+      node_idx(m, node, idx);
+      double acc[5] = {0, 0, 0, 0, 0}, f[5];
+      for (int i = 0; i < 3; ++i) {
+        const int id = idx[i];
+        double ai[3];
+        curv_ja(c, i, e, node, ai);
+        if (cfg->volume != ORC_VOL_NONE) {
+          for (int mm = 0; mm < n; ++mm) {
+            if (mm == id) continue;
+            int pidx[3] = {idx[0], idx[1], idx[2]};
+            pidx[i] = mm;
+            const int pn = node_of(m, pidx);
+            double ap[3], abar[3];
+            curv_ja(c, i, e, pn, ap);
+            for (int k = 0; k < 3; ++k) abar[k] = 0.5 * (ai[k] + ap[k]);
+            vol_flux_curv(cfg->volume, ue[node], &qe[node], ue[pn], &qe[pn], abar, gamma, f);
+            for (int v = 0; v < 5; ++v) acc[v] = acc[v] + m->S[id * n + mm] * f[v];
+          }
+        }
+        if (cfg->surface != ORC_SURF_NONE && (id == 0 || id == N)) {
+          int pidx[3] = {idx[0], idx[1], idx[2]};
+          double un[5];
+          prim_t qn;
+          if (id == N) {
+            pidx[i] = 0;
+            load_node(m, u, neighbour(m, e, i, +1), node_of(m, pidx), un);
+            bad |= to_prim(un, 3, gamma, &qn);
+            surf_flux_curv(cfg->surface, ue[node], &qe[node], un, &qn, ai, gamma, f);
+            for (int v = 0; v < 5; ++v) acc[v] = acc[v] + f[v] / m->w[N];
+          }
+          if (id == 0) {
+            pidx[i] = N;
+            load_node(m, u, neighbour(m, e, i, -1), node_of(m, pidx), un);
+            bad |= to_prim(un, 3, gamma, &qn);
+            surf_flux_curv(cfg->surface, un, &qn, ue[node], &qe[node], ai, gamma, f);
+            for (int v = 0; v < 5; ++v) acc[v] = acc[v] - f[v] / m->w[0];
+          }
+        }
+      }
+      const double Jn = c->J[e * NN + node];
+      double s[5] = {0, 0, 0, 0, 0};
+      if (cfg->source == ORC_SRC_MMS) {
+        double x[3];
+        for (int d = 0; d < 3; ++d) x[d] = c->xyz[((int64_t)d * m->E + e) * NN + node];
+        orc_curv_mms(gamma, x, t, NULL, s);
+      }
+      for (int v = 0; v < 5; ++v) du[((int64_t)v * m->E + e) * NN + node] = -acc[v] / Jn + s[v];
+    }
+  }
+  return bad ? ORC_ENONPHYS : ORC_OK;
+}
+
+int orc_curv_rhs(const orc_curv_config *cfg, const double *u, double t, double *du)
+{
+  curv_t c;
+  memset(&c, 0, sizeof(c));
+  int st = curv_setup(cfg, &c);
+  if (st == ORC_OK) st = curv_rhs_core(cfg, &c, u, t, du);
+  curv_free(&c);
+  return st;
+}
+
+int orc_curv_initial(const orc_curv_config *cfg, double t, double *u)
+{
+  curv_t c;
+  memset(&c, 0, sizeof(c));
+  int st = curv_setup(cfg, &c);
+  if (st == ORC_OK) {
+    const int64_t len = c.m.E * c.m.NN;
+    for (int64_t i = 0; i < len; ++i) {
+      double x[3] = {c.xyz[i], c.xyz[len + i], c.xyz[2 * len + i]}, un[5];
+      orc_curv_mms(cfg->gamma, x, t, un, NULL);
+      for (int v = 0; v < 5; ++v) u[v * len + i] = un[v];
+    }
+  }
+  curv_free(&c);
+  return st;
+}
+
+/* dt = cfl 2 / ((N+1) max_e sum_i max_{nodes} (|Ja^i . v| + c |Ja^i|) / J): the Cartesian
+ * rule with 2/h_d (|v_d| + c) replaced by its contravariant counterpart. */
+static int curv_max_dt_core(const orc_curv_config *cfg, const curv_t *c, const double *u,
+                            double cfl, double *dt)
+{
+  const mesh_t *m = &c->m;
+  const int NN = m->NN;
+  double lmax = 0.0;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(max : lmax) reduction(| : bad)
+  for (int64_t e = 0; e < m->E; ++e) {
+    double lam = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      double mx = 0.0;
+      for (int node = 0; node < NN; ++node) {
+        double un[5], a[3];
+        prim_t q;
+        load_node(m, u, e, node, un);
+        bad |= to_prim(un, 3, cfg->gamma, &q);
+        curv_ja(c, i, e, node, a);
+        const double an = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+        const double va = q.v[0] * a[0] + q.v[1] * a[1] + q.v[2] * a[2];
+        const double l = (fabs(va) + q.c * an) / c->J[e * NN + node];
+        if (l > mx) mx = l;
+      }
+      lam = lam + mx;
+    }
+    if (lam > lmax) lmax = lam;
+  }
+  *dt = cfl * 2.0 / ((m->N + 1) * lmax);
+  return bad ? ORC_ENONPHYS : ORC_OK;
+}
+
+int orc_curv_max_dt(const orc_curv_config *cfg, const double *u, double cfl, double *dt)
+{
+  curv_t c;
+  memset(&c, 0, sizeof(c));
+  int st = curv_setup(cfg, &c);
+  if (st == ORC_OK) st = curv_max_dt_core(cfg, &c, u, cfl, dt);
+  curv_free(&c);
+  return st;
+}
+
+/* CK(5,4) with stage times t + c_s dt for the time-dependent source. */
+int orc_curv_step(const orc_curv_config *cfg, double *u, int32_t nsteps, double cfl,
+                  double dt_fixed, double *t)
+{
+  curv_t c;
+  memset(&c, 0, sizeof(c));
+  int st = curv_setup(cfg, &c);
+  if (st) {
+    curv_free(&c);
+    return st;
+  }
+  const int64_t len = 5 * c.m.E * c.m.NN;
+  double *k = calloc(len, sizeof(double)), *du = malloc(sizeof(double) * len);
+  double A[5], B[5], cs[5];
+  orc_lsrk_coeffs(A, B, cs);
+  double tt = t ? *t : 0.0;
+  for (int step = 0; step < nsteps && st == ORC_OK; ++step) {
+    double dt = dt_fixed;
+    if (cfl > 0.0) st = curv_max_dt_core(cfg, &c, u, cfl, &dt);
+    for (int s = 0; s < 5 && st == ORC_OK; ++s) {
+      st = curv_rhs_core(cfg, &c, u, tt + cs[s] * dt, du);
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < len; ++i) {
+        k[i] = A[s] * k[i] + dt * du[i];
+        u[i] = u[i] + B[s] * k[i];
+      }
+    }
+    tt = tt + dt;
+  }
+  if (t) *t = tt;
+  free(k);
+  free(du);
+  curv_free(&c);
+  return st;
+}

@@ -86,6 +86,36 @@ int orc_step(const orc_config *cfg, double *u, int32_t nsteps, double cfl, doubl
 int orc_integrals(const orc_config *cfg, const double *u, const double *du, double *out7);
 int orc_num_threads(void);
 
+/* Curvilinear mesh of the PID study (Section 3.1): the periodic box [-1,1]^3 with cells^3
+ * elements, mapped by Eq. (2) with amplitude warp (0.15 in the paper; 0 gives the Cartesian
+ * grid).  Reference-element node positions are mapped; metric terms (J a^i)_n come from the
+ * conservative curl form of the interpolated mapping, J from the interpolant's derivatives.
+ * Volume: flux differencing with the two-point flux contracted with the averaged metric
+ * vector; surface: the interface flux through the face's contravariant vector.
+ * source = ORC_SRC_MMS adds the manufactured solution's source term (orc_curv_mms). */
+enum { ORC_SRC_NONE = 0, ORC_SRC_MMS = 1 };
+typedef struct {
+  int32_t polydeg;
+  int32_t cells;      /* elements per direction */
+  double  warp;       /* amplitude of the Eq. (2) mapping */
+  double  gamma;
+  int32_t volume;     /* ORC_VOL_EC, ORC_VOL_CENTRAL or ORC_VOL_NONE */
+  int32_t surface;    /* ORC_SURF_* */
+  int32_t source;     /* ORC_SRC_* */
+} orc_curv_config;
+
+int orc_curv_map(double warp, const double *xi, double *x);               /* Eq. (2) */
+/* the manufactured solution u(x, t) and its source s(x, t) (either may be NULL) */
+int orc_curv_mms(double gamma, const double *x, double t, double *u, double *s);
+int64_t orc_curv_num_nodes(const orc_curv_config *cfg);
+/* xyz [3][E][n^3], Ja [3 (i)][3 (n)][E][n^3] = (J a^i)_n, J [E][n^3]; any may be NULL */
+int orc_curv_geometry(const orc_curv_config *cfg, double *xyz, double *Ja, double *J);
+int orc_curv_initial(const orc_curv_config *cfg, double t, double *u);   /* MMS at nodes */
+int orc_curv_rhs(const orc_curv_config *cfg, const double *u, double t, double *du);
+int orc_curv_max_dt(const orc_curv_config *cfg, const double *u, double cfl, double *dt);
+int orc_curv_step(const orc_curv_config *cfg, double *u, int32_t nsteps, double cfl,
+                  double dt_fixed, double *t);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,8 @@ from . import build as _build
 
 __all__ = ["Oracle", "OracleError", "NonPhysicalState", "lgl", "legendre_vinv", "ln_mean",
            "flux_phys", "flux_ec", "flux_central", "flux_llf", "flux_hll", "entropy",
-           "entropy_vars", "lsrk_coeffs", "num_threads", "VOLUME", "SURFACE", "lib"]
+           "entropy_vars", "lsrk_coeffs", "num_threads", "VOLUME", "SURFACE", "lib",
+           "CurvOracle", "curv_map", "curv_mms"]
 
 VOLUME = {"ec": 0, "central": 1, "shockcap_hg": 2, "weak": 3, "none": 4}
 SURFACE = {"llf": 0, "hll": 1, "ec": 2, "none": 3}
@@ -32,6 +33,12 @@ class _Cfg(C.Structure):
                 ("volume", C.c_int32), ("surface", C.c_int32), ("fv_flux", C.c_int32),
                 ("alpha_max", C.c_double), ("alpha_min", C.c_double),
                 ("alpha_smooth", C.c_int32)]
+
+
+class _CurvCfg(C.Structure):
+    _fields_ = [("polydeg", C.c_int32), ("cells", C.c_int32), ("warp", C.c_double),
+                ("gamma", C.c_double), ("volume", C.c_int32), ("surface", C.c_int32),
+                ("source", C.c_int32)]
 
 
 _lib = None
@@ -67,6 +74,15 @@ def lib():
             ("orc_step", [CP, P, C.c_int32, C.c_double, C.c_double, P], C.c_int),
             ("orc_integrals", [CP, P, P, P], C.c_int),
             ("orc_num_threads", [], C.c_int),
+            ("orc_curv_map", [C.c_double, P, P], C.c_int),
+            ("orc_curv_mms", [C.c_double, P, C.c_double, P, P], C.c_int),
+            ("orc_curv_num_nodes", [C.POINTER(_CurvCfg)], C.c_int64),
+            ("orc_curv_geometry", [C.POINTER(_CurvCfg), P, P, P], C.c_int),
+            ("orc_curv_initial", [C.POINTER(_CurvCfg), C.c_double, P], C.c_int),
+            ("orc_curv_rhs", [C.POINTER(_CurvCfg), P, C.c_double, P], C.c_int),
+            ("orc_curv_max_dt", [C.POINTER(_CurvCfg), P, C.c_double, P], C.c_int),
+            ("orc_curv_step", [C.POINTER(_CurvCfg), P, C.c_int32, C.c_double, C.c_double, P],
+             C.c_int),
         ]:
             f = getattr(L, name)
             f.argtypes = args
@@ -252,3 +268,74 @@ class Oracle:
         dd = None if du is None else self._u(du)
         _check(lib().orc_integrals(C.byref(self.cfg), _p(u), _p(dd), _p(out)), "integrals")
         return out
+
+
+# --------------------------------------------------------------------------- curvilinear
+def curv_map(xi, warp=0.15):
+    """The Eq. (2) mapping of one reference point."""
+    x = np.zeros(3)
+    _check(lib().orc_curv_map(float(warp), _p(_f64(xi)), _p(x)), "curv_map")
+    return x
+
+
+def curv_mms(x, t, gamma=1.4):
+    """Manufactured solution u(x, t) and its source s(x, t) at one point."""
+    u, s = np.zeros(5), np.zeros(5)
+    _check(lib().orc_curv_mms(gamma, _p(_f64(x)), float(t), _p(u), _p(s)), "curv_mms")
+    return u, s
+
+
+class CurvOracle:
+    """The warped periodic box of the PID study (cells^3 elements on [-1,1]^3, Eq. (2))."""
+
+    def __init__(self, polydeg, cells, warp=0.15, gamma=1.4, volume="ec", surface="llf",
+                 source="mms"):
+        c = _CurvCfg()
+        c.polydeg, c.cells, c.warp, c.gamma = polydeg, cells, warp, gamma
+        c.volume = VOLUME[volume]
+        c.surface = SURFACE[surface]
+        c.source = {"none": 0, "mms": 1}[source]
+        self.cfg = c
+        self.N, self.K, self.n = polydeg, cells, polydeg + 1
+        self.NN = self.n ** 3
+        self.E = cells ** 3
+        self.dim = 3
+        if lib().orc_curv_num_nodes(C.byref(c)) < 0:
+            raise OracleError("invalid curvilinear configuration")
+
+    def _u(self, u):
+        u = _f64(u)
+        if u.size != 5 * self.E * self.NN:
+            raise ValueError("state has the wrong size")
+        return u
+
+    def geometry(self):
+        n = self.E * self.NN
+        xyz, Ja, J = np.zeros(3 * n), np.zeros(9 * n), np.zeros(n)
+        _check(lib().orc_curv_geometry(C.byref(self.cfg), _p(xyz), _p(Ja), _p(J)), "geometry")
+        return (xyz.reshape(3, self.E, self.NN), Ja.reshape(3, 3, self.E, self.NN),
+                J.reshape(self.E, self.NN))
+
+    def initial(self, t=0.0):
+        u = np.zeros((5, self.E, self.NN))
+        _check(lib().orc_curv_initial(C.byref(self.cfg), float(t), _p(u)), "initial")
+        return u
+
+    def rhs(self, u, t=0.0):
+        u = self._u(u)
+        du = np.zeros_like(u)
+        _check(lib().orc_curv_rhs(C.byref(self.cfg), _p(u), float(t), _p(du)), "rhs")
+        return du.reshape(5, self.E, self.NN)
+
+    def max_dt(self, u, cfl):
+        dt = C.c_double(0.0)
+        _check(lib().orc_curv_max_dt(C.byref(self.cfg), _p(self._u(u)), cfl, C.byref(dt)),
+               "max_dt")
+        return dt.value
+
+    def step(self, u, nsteps, cfl=0.5, dt_fixed=0.0, t=0.0):
+        u = self._u(u).copy()
+        tt = C.c_double(t)
+        _check(lib().orc_curv_step(C.byref(self.cfg), _p(u), int(nsteps), cfl, dt_fixed,
+                                   C.byref(tt)), "step")
+        return u.reshape(5, self.E, self.NN), tt.value
