@@ -107,9 +107,9 @@ def main():
     ap.add_argument("--workload", default="tgv_32")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="rhs,mixed,batched,sedov,weak,dwave",
+    ap.add_argument("--variants", default="rhs,mixed,batched,sedov,weak,curved,dwave",
                     help="comma list of extra variants: rhs, mixed, batched, sedov, weak, "
-                         "dwave ('' for none)")
+                         "curved, dwave ('' for none)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -196,6 +196,12 @@ def main():
                 variants[f"{vol}_hll_tgv_32_fp64"] = bench_weak(args, vol)
             except Exception as e:
                 variants[f"{vol}_hll_tgv_32_fp64"] = {"error": str(e)}
+    if "curved" in want:
+        for name in ("curved_4", "curved_32"):
+            try:
+                variants[f"{name}_mms_fp64"] = bench_curved(args, name)
+            except Exception as e:
+                variants[f"{name}_mms_fp64"] = {"error": str(e)}
     if "dwave" in want:
         try:
             variants["density_wave_2d_fp64"] = bench_density_wave(args)
@@ -278,6 +284,32 @@ def bench_weak(args, volume="weak"):
     gbs = 152.0 * s.num_nodes / (avg_ms * 1e-3) / 1e9
     return {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps,
             "stage_us": round(avg_ms * 1e3, 2), "stage_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+def bench_curved(args, name):
+    """The PID study's curvilinear mesh (warped box, Eq. (2)) with the manufactured solution's
+    source term, EC + LLF, N = 3: full RK steps; curved_4 is the paper's 4^3 mesh (4096
+    nodes: launch-bound), curved_32 the same per-GPU size as tgv_32."""
+    import torch
+
+    from paper_2108_06476_amd import dgx, inputs
+    s = dgx.CurvSolver(**inputs.workload(name))
+    u = inputs.mms(s.node_coords()).contiguous()
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    steps = max(10, args.steps // 2)
+    s.step(u, 2, cfl=0.5, t=t)
+    torch.cuda.synchronize()
+    s.profile_enable(True)
+    t0 = time.perf_counter()
+    s.step(u, steps, cfl=0.5, t=t)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    avg_ms, _, _ = s.profile_read()
+    s.profile_enable(False)
+    if s.check():
+        raise RuntimeError("non-physical state during the benchmark")
+    return {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps,
+            "ms_per_step": secs / steps * 1e3, "stage_us": round(avg_ms * 1e3, 2)}
 
 
 def kernel_source_hash():

@@ -110,7 +110,8 @@ dgx_status dgx_node_coords(dgx_handle h, double *xyz);
 
 /* du = R(u): the semidiscrete right-hand side du/dt (Eq. (1) discretised).  u, du
  * are device [nvar][E][n^dim] and must not overlap.  For DGX_VOL_SHOCKCAP_HG the
- * indicator is evaluated from u first.  t is unused (no source terms). */
+ * indicator is evaluated from u first.  t: the time of a source term (curvilinear handles
+ * with DGX_SOURCE_MMS; unused otherwise). */
 dgx_status dgx_rhs(dgx_handle h, const double *u, double *du, double t);
 
 /* Hennemann-Gassner indicator of u: alpha[E] (device), clipped and, when
@@ -145,6 +146,45 @@ dgx_status dgx_check(dgx_handle h, int32_t *flag);
 
 /* The handle's last error message (host string owned by the handle). */
 const char *dgx_last_error(dgx_handle h);
+
+/* ---- curvilinear mesh (the PID study's geometry, Section 3.1) ------------------------
+ * The periodic box [-1,1]^3 with cells^3 hexahedra, warped by the mapping of Eq. (2)
+ * (amplitude warp; 0.15 in the paper, 0 = Cartesian):
+ *   y = eta + warp cos(1.5 pi xi) cos(0.5 pi eta) cos(0.5 pi zeta),
+ *   x = xi  + warp cos(0.5 pi xi) cos(2 pi y)     cos(0.5 pi zeta),
+ *   z = zeta + warp cos(0.5 pi x) cos(pi y)       cos(0.5 pi zeta).
+ * The element nodes are the mapped LGL points; metric terms (J a^i)_n come from the
+ * conservative curl form of the interpolated mapping (discrete metric identities hold, so a
+ * constant state stays constant), J from the interpolant's derivatives.  The two-point
+ * volume flux is contracted with the pair's averaged metric vector; interface fluxes pass
+ * through the face's contravariant vector; du/dt = -(1/J)(...) + s(x, t).
+ * source = DGX_SOURCE_MMS adds the source of the manufactured solution
+ *   rho = 2 + 0.1 sin(pi (x + y + z) - 2 pi t), v = (1, 1, 1), rho E = rho^2
+ * (the paper's Euler test is a manufactured solution with sine/cosine source terms, which
+ * it does not print; this one is the library's reading).  Stage times t + c_s dt. */
+typedef enum { DGX_SOURCE_NONE = 0, DGX_SOURCE_MMS = 1 } dgx_source;
+
+typedef struct {
+  int32_t polydeg;        /* N; compiled for 1..7 */
+  int32_t cells;          /* elements per direction */
+  double  warp;           /* Eq. (2) amplitude, 0 <= warp < 0.5 */
+  double  gamma;          /* > 1 */
+  int32_t volume;         /* DGX_VOL_EC, DGX_VOL_CENTRAL or DGX_VOL_NONE (else EUNSUPPORTED) */
+  int32_t surface;        /* dgx_surface */
+  int32_t source;         /* dgx_source */
+} dgx_curv_config;
+
+/* A solver on the curvilinear mesh (FP64).  The handle works with dgx_rhs (t is the time
+ * of the source term), dgx_step (t required with a source: the stages use its value at the
+ * start of each step), dgx_max_dt (dt from sum_i max (|v . Ja^i| + c |Ja^i|)/J),
+ * dgx_node_coords (the mapped positions), dgx_check and the profiling calls;
+ * dgx_indicator, dgx_rhs_alpha and dgx_integrals return DGX_EUNSUPPORTED on it.
+ * Computes the geometry on the device (synchronises the stream once). */
+dgx_status dgx_create_curved(const dgx_curv_config *cfg, void *hip_stream, dgx_handle *out);
+
+/* The geometry of a curvilinear handle: ja [3 (i)][3 (n)][E][n^3] = (J a^i)_n and
+ * jac [E][n^3] = J (device; either may be NULL).  DGX_EINVAL on a Cartesian handle. */
+dgx_status dgx_geometry(dgx_handle h, double *ja, double *jac);
 
 /* Kernel timing for benchmarks: enables HIP-event timing of the dominant (stage) kernel on
  * the handle's stream.  One event pair brackets each run of back-to-back stage launches

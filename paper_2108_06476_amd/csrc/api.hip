@@ -68,23 +68,36 @@ static const double CK_B[5] = {1432997174477.0 / 9575080441755.0,
                                3134564353537.0 / 4481467310338.0,
                                2277821191437.0 / 14882151754819.0};
 
-// dt = cfl * 2 / ((N+1) * max partial); t += dt
+// Stage times c_s of the same scheme (for time-dependent source terms: t + c_s dt).
+static const double CK_C[5] = {0.0, 1432997174477.0 / 9575080441755.0,
+                               2526269341429.0 / 6820363183890.0,
+                               2006345519317.0 / 3224310063776.0,
+                               2802321613138.0 / 2924317926251.0};
+
+// dt = cfl * 2 / ((N+1) * max partial); t0 = t (the step's start time, when asked); t += dt
 __global__ __launch_bounds__(1024) void k_dt_final(const double* __restrict__ partial, int64_t np,
                                                    double cfl, double n1, double* __restrict__ dt,
-                                                   double* __restrict__ t) {
+                                                   double* __restrict__ t, double* __restrict__ t0) {
   __shared__ double s[16];
   const double m = block_max<1024>(partial, np, s);
   if (threadIdx.x == 0) {
     const double d = cfl * 2.0 / (n1 * m);
     *dt = d;
-    if (t) *t += d;
+    if (t) {
+      if (t0) *t0 = *t;
+      *t += d;
+    }
   }
 }
 
-__global__ void k_set_dt(double v, double* __restrict__ dt, double* __restrict__ t) {
+__global__ void k_set_dt(double v, double* __restrict__ dt, double* __restrict__ t,
+                         double* __restrict__ t0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     *dt = v;
-    if (t) *t += v;
+    if (t) {
+      if (t0) *t0 = *t;
+      *t += v;
+    }
   }
 }
 
@@ -138,6 +151,13 @@ struct dgx_solver {
   int64_t nblk = 0;    // blocks of the element-tiled kernels (integral partials)
   double* dt = nullptr;
   int* flag = nullptr;
+  // curvilinear mesh (dgx_create_curved)
+  bool curved = false;
+  double* ja = nullptr;     // (J a^i)_n [3][3][E][NN]
+  double* jac = nullptr;    // J [E][NN]
+  double* xyz = nullptr;    // node positions [3][E][NN]
+  double* dmat = nullptr;   // LGL differentiation matrix [n][n]
+  double* t0 = nullptr;     // start time of the current step
   std::string err;
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -212,7 +232,8 @@ hipError_t launch_stage(dgx_handle h, const StageArgs& a, int epi, bool last) {
     hipError_t r = hipEventRecord(h->ev[h->ev_used], h->stream);
     if (r != hipSuccess) return r;
   }
-  hipError_t r = h->L->stage(h->stream, a, h->g, h->cfg.volume, epi, h->cfg.precision);
+  hipError_t r = h->curved ? h->L->stage_curv(h->stream, a, h->g, h->cfg.volume, epi)
+                           : h->L->stage(h->stream, a, h->g, h->cfg.volume, epi, h->cfg.precision);
   if (r != hipSuccess || !h->prof) return r;
   h->ev_count[pair] += 1;
   if (last) {   // close it
@@ -246,7 +267,8 @@ StageArgs stage_args(dgx_handle h, const double* uin, const double* alpha) {
 }
 
 // du = R(u); alpha_in (shock capturing) may be NULL: then the indicator runs first.
-dgx_status enqueue_rhs(dgx_handle h, const double* u, double* du, const double* alpha_in) {
+dgx_status enqueue_rhs(dgx_handle h, const double* u, double* du, const double* alpha_in,
+                       double t = 0.0) {
   const double* alpha = alpha_in;
   if (h->cfg.volume == DGX_VOL_SHOCKCAP_HG && !alpha) {
     dgx_status st = enqueue_indicator(h, u, h->alpha, h->alpha_raw, nullptr);
@@ -255,18 +277,22 @@ dgx_status enqueue_rhs(dgx_handle h, const double* u, double* du, const double* 
   }
   StageArgs a = stage_args(h, u, alpha);
   a.du = du;
+  a.t = t;
   HIPCHK(h, launch_stage(h, a, EPI_RHS, true));
   return DGX_OK;
 }
 
-}  // namespace
 
-extern "C" {
+// Per-element CFL partials of u into h->partial.
+hipError_t enqueue_maxspeed(dgx_handle h, const double* u) {
+  return h->curved ? h->L->maxspeed_curv(h->stream, u, h->partial, h->g)
+                   : h->L->maxspeed(h->stream, u, h->partial, h->g);
+}
 
-dgx_status dgx_create(const dgx_config* cfg, void* hip_stream, dgx_handle* out) {
-  if (!cfg || !out) return DGX_EINVAL;
+// The solver behind dgx_create (cv == nullptr) and dgx_create_curved.
+dgx_status create_impl(const dgx_config& c, const dgx_curv_config* cv, void* hip_stream,
+                       dgx_handle* out) {
   *out = nullptr;
-  const dgx_config& c = *cfg;
   if (c.dim != 2 && c.dim != 3) return DGX_EINVAL;
   if (c.polydeg < 1) return DGX_EINVAL;
   if (!(c.gamma > 1.0)) return DGX_EINVAL;
@@ -304,14 +330,17 @@ dgx_status dgx_create(const dgx_config* cfg, void* hip_stream, dgx_handle* out) 
   }
   h->stream = (hipStream_t)hip_stream;
   h->L = L;
-  if ((int64_t)h->NV * h->E * h->NN >= ((int64_t)1 << 31)) {   // kernels index in 32 bits
+  const int64_t nodes = h->E * h->NN;
+  if ((int64_t)(cv ? 9 : h->NV) * nodes >= ((int64_t)1 << 31)) {   // kernels index in 32 bits
     delete h;
     return DGX_EUNSUPPORTED;
   }
+  // curvilinear: the reference element's tables (2/h = 1); the metric terms carry the scale
+  const double href[3] = {2.0, 2.0, 2.0};
 
   // operator tables
   std::vector<double> T(TAB_SIZE, 0.0);
-  if (!stage_tables(h->N, h->h, T.data(),
+  if (!stage_tables(h->N, cv ? href : h->h, T.data(),
                     c.volume == DGX_VOL_WEAK || c.volume == DGX_VOL_WEAK_MFMA)) {
     delete h;
     return DGX_EINVAL;
@@ -352,7 +381,83 @@ dgx_status dgx_create(const dgx_config* cfg, void* hip_stream, dgx_handle* out) 
   h->g.gamma = c.gamma;
   h->g.tab = h->tab;
   h->g.flag = h->flag;
+  if (cv) {
+    h->curved = true;
+    const int n = h->n;
+    double x[16], w[16], D[256], Vinv[256];
+    if (!lgl_tables(h->N, x, w, D, Vinv)) {
+      dgx_destroy(h);
+      return DGX_EINVAL;
+    }
+    if (!alloc((void**)&h->ja, sizeof(double) * 9 * nodes) ||
+        !alloc((void**)&h->jac, sizeof(double) * nodes) ||
+        !alloc((void**)&h->xyz, sizeof(double) * 3 * nodes) ||
+        !alloc((void**)&h->dmat, sizeof(double) * n * n) || !alloc((void**)&h->t0, sizeof(double))) {
+      dgx_destroy(h);
+      return DGX_ENOMEM;
+    }
+    if (hipMemcpy(h->dmat, D, sizeof(double) * n * n, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(h->t0, 0, sizeof(double)) != hipSuccess ||
+        h->L->geometry(h->stream, h->g, h->dmat, cv->warp, h->xyz, h->ja, h->jac) != hipSuccess ||
+        hipStreamSynchronize(h->stream) != hipSuccess) {
+      dgx_destroy(h);
+      return DGX_EHIP;
+    }
+    h->g.ja = h->ja;
+    h->g.jac = h->jac;
+    h->g.xyz = h->xyz;
+    h->g.source = cv->source == DGX_SOURCE_MMS ? 1 : 0;
+  }
   *out = h;
+  return DGX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+dgx_status dgx_create(const dgx_config* cfg, void* hip_stream, dgx_handle* out) {
+  if (!cfg || !out) return DGX_EINVAL;
+  return create_impl(*cfg, nullptr, hip_stream, out);
+}
+
+dgx_status dgx_create_curved(const dgx_curv_config* cv, void* hip_stream, dgx_handle* out) {
+  if (!cv || !out) return DGX_EINVAL;
+  *out = nullptr;
+  if (cv->polydeg < 1 || cv->cells < 1 || !(cv->gamma > 1.0) || !(cv->warp >= 0.0 && cv->warp < 0.5))
+    return DGX_EINVAL;
+  if (cv->volume != DGX_VOL_EC && cv->volume != DGX_VOL_CENTRAL && cv->volume != DGX_VOL_NONE)
+    return DGX_EUNSUPPORTED;
+  if (cv->surface < DGX_SURF_LLF || cv->surface > DGX_SURF_NONE) return DGX_EINVAL;
+  if (cv->source != DGX_SOURCE_NONE && cv->source != DGX_SOURCE_MMS) return DGX_EINVAL;
+  dgx_config c{};
+  c.dim = 3;
+  c.polydeg = cv->polydeg;
+  for (int d = 0; d < 3; ++d) {
+    c.cells[d] = cv->cells;
+    c.xmin[d] = -1.0;
+    c.xmax[d] = 1.0;
+  }
+  c.gamma = cv->gamma;
+  c.volume = cv->volume;
+  c.surface = cv->surface;
+  c.fv_flux = DGX_SURF_LLF;
+  c.precision = DGX_FP64;
+  return create_impl(c, cv, hip_stream, out);
+}
+
+dgx_status dgx_geometry(dgx_handle h, double* ja, double* jac) {
+  if (!h) return DGX_EINVAL;
+  if (!h->curved) return fail(h, DGX_EINVAL, "dgx_geometry needs a curvilinear handle");
+  const size_t nodes = (size_t)h->E * h->NN;
+  if (ja) {
+    CHKDEV(h, ja, sizeof(double) * 9 * nodes, "ja");
+    HIPCHK(h, hipMemcpyAsync(ja, h->ja, sizeof(double) * 9 * nodes, hipMemcpyDeviceToDevice, h->stream));
+  }
+  if (jac) {
+    CHKDEV(h, jac, sizeof(double) * nodes, "jac");
+    HIPCHK(h, hipMemcpyAsync(jac, h->jac, sizeof(double) * nodes, hipMemcpyDeviceToDevice, h->stream));
+  }
   return DGX_OK;
 }
 
@@ -361,7 +466,8 @@ dgx_status dgx_destroy(dgx_handle h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   else (void)hipDeviceSynchronize();
   for (void* p : {(void*)h->tab, (void*)h->u2, (void*)h->k, (void*)h->alpha, (void*)h->alpha_raw,
-                  (void*)h->energy, (void*)h->partial, (void*)h->dt, (void*)h->flag})
+                  (void*)h->energy, (void*)h->partial, (void*)h->dt, (void*)h->flag, (void*)h->ja,
+                  (void*)h->jac, (void*)h->xyz, (void*)h->dmat, (void*)h->t0})
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   delete h;
@@ -380,22 +486,26 @@ int64_t dgx_num_elements(dgx_handle h) { return h ? h->E : -1; }
 dgx_status dgx_node_coords(dgx_handle h, double* xyz) {
   if (!h) return DGX_EINVAL;
   CHKDEV(h, xyz, sizeof(double) * (size_t)h->dim * h->E * h->NN, "xyz");
+  if (h->curved) {
+    HIPCHK(h, hipMemcpyAsync(xyz, h->xyz, sizeof(double) * 3 * (size_t)h->E * h->NN,
+                             hipMemcpyDeviceToDevice, h->stream));
+    return DGX_OK;
+  }
   HIPCHK(h, h->L->coords(h->stream, xyz, h->g, h->cfg.xmin));
   return DGX_OK;
 }
 
 dgx_status dgx_rhs(dgx_handle h, const double* u, double* du, double t) {
-  (void)t;
   if (!h) return DGX_EINVAL;
   CHKDEV(h, u, state_bytes(h), "u");
   CHKDEV(h, du, state_bytes(h), "du");
   if (u == du) return fail(h, DGX_EINVAL, "u and du must not overlap");
-  return enqueue_rhs(h, u, du, nullptr);
+  return enqueue_rhs(h, u, du, nullptr, t);
 }
 
 dgx_status dgx_rhs_alpha(dgx_handle h, const double* u, const double* alpha, double* du) {
   if (!h) return DGX_EINVAL;
-  if (h->cfg.volume != DGX_VOL_SHOCKCAP_HG)
+  if (h->cfg.volume != DGX_VOL_SHOCKCAP_HG || h->curved)
     return fail(h, DGX_EINVAL, "dgx_rhs_alpha needs DGX_VOL_SHOCKCAP_HG");
   CHKDEV(h, u, state_bytes(h), "u");
   CHKDEV(h, du, state_bytes(h), "du");
@@ -407,6 +517,7 @@ dgx_status dgx_rhs_alpha(dgx_handle h, const double* u, const double* alpha, dou
 dgx_status dgx_indicator(dgx_handle h, const double* u, double* alpha, double* alpha_raw,
                          double* energy) {
   if (!h) return DGX_EINVAL;
+  if (h->curved) return fail(h, DGX_EUNSUPPORTED, "no indicator on curvilinear handles");
   CHKDEV(h, u, state_bytes(h), "u");
   CHKDEV(h, alpha, sizeof(double) * h->E, "alpha");
   if (alpha_raw) CHKDEV(h, alpha_raw, sizeof(double) * h->E, "alpha_raw");
@@ -420,9 +531,9 @@ dgx_status dgx_max_dt(dgx_handle h, const double* u, double cfl, double* dt) {
   if (!(cfl > 0.0)) return fail(h, DGX_EINVAL, "cfl must be > 0");
   CHKDEV(h, u, state_bytes(h), "u");
   CHKDEV(h, dt, sizeof(double), "dt");
-  HIPCHK(h, h->L->maxspeed(h->stream, u, h->partial, h->g));
+  HIPCHK(h, enqueue_maxspeed(h, u));
   hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, h->stream, h->partial, h->npart, cfl,
-                     (double)(h->N + 1), dt, (double*)nullptr);
+                     (double)(h->N + 1), dt, (double*)nullptr, (double*)nullptr);
   HIPCHK(h, hipGetLastError());
   return DGX_OK;
 }
@@ -434,20 +545,22 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
   if (!(cfl > 0.0) && !(dt_fixed > 0.0)) return fail(h, DGX_EINVAL, "need cfl > 0 or dt_fixed > 0");
   CHKDEV(h, u, state_bytes(h), "u");
   if (t) CHKDEV(h, t, sizeof(double), "t");
+  if (h->g.source && !t) return fail(h, DGX_EINVAL, "the source term needs the device time t");
   if (nsteps == 0) return DGX_OK;
+  double* t0 = h->g.source ? h->t0 : nullptr;   // step start time for the stage times
   const bool adaptive = cfl > 0.0;
   // the state alternates between u and the library's u2, stage by stage: a stage reads the
   // neighbours' face states of its input while other blocks write their output
   double* buf[2] = {u, h->u2};
   int cur = 0;
-  if (adaptive) HIPCHK(h, h->L->maxspeed(h->stream, u, h->partial, h->g));
+  if (adaptive) HIPCHK(h, enqueue_maxspeed(h, u));
   for (int s = 0; s < nsteps; ++s) {
     if (adaptive) {
       // partials: from the wave-speed pass (first step) or from the last stage of the step before
       hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, h->stream, h->partial, h->npart, cfl,
-                         (double)(h->N + 1), h->dt, t);
+                         (double)(h->N + 1), h->dt, t, t0);
     } else {
-      hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, h->stream, dt_fixed, h->dt, t);
+      hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, h->stream, dt_fixed, h->dt, t, t0);
     }
     HIPCHK(h, hipGetLastError());
     for (int st = 0; st < 5; ++st) {
@@ -463,6 +576,8 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
       a.A = CK_A[st];
       a.B = CK_B[st];
       a.speed = (adaptive && st == 4 && s + 1 < nsteps) ? h->partial : nullptr;
+      a.t0 = t0;
+      a.cs = CK_C[st];
       // stages of one step run back to back unless indicator kernels sit between them
       HIPCHK(h, launch_stage(h, a, EPI_RK, st == 4 || alpha != nullptr));
       cur = 1 - cur;
@@ -478,6 +593,7 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
 
 dgx_status dgx_integrals(dgx_handle h, const double* u, const double* du, double* out7) {
   if (!h) return DGX_EINVAL;
+  if (h->curved) return fail(h, DGX_EUNSUPPORTED, "no integrals on curvilinear handles");
   CHKDEV(h, u, state_bytes(h), "u");
   if (du) CHKDEV(h, du, state_bytes(h), "du");
   CHKDEV(h, out7, sizeof(double) * 7, "out7");

@@ -1,0 +1,358 @@
+// curv.h -- curvilinear hexahedral elements (the warped periodic box of the PID study,
+// Section 3.1, Eq. (2)): geometry, the fused RK stage with metric terms and the
+// manufactured solution's source term, and the CFL wave-speed pass.
+//
+// Geometry (per element, from the LGL nodes mapped by Eq. (2)): the interpolant's
+// derivatives dX/ds_j by the differentiation matrix, J = dX/ds_0 . (dX/ds_1 x dX/ds_2), and
+// the metric terms in the conservative curl form
+//   (J a^i)_n = -[curl_s (X_l grad_s X_m)]_i,   (n, m, l) cyclic,
+// which satisfy the discrete metric identities sum_i d/ds_i (J a^i) = 0 node by node (a
+// constant state stays constant) and agree on both sides of every face.
+// Semidiscretisation (reference element, no 2/h):
+//   du/dt = -(1/J) sum_i [ sum_m S_im f~#_i(u, u_m) + (face terms with F~*)/w ] + s(x, t),
+// f~#_i(A, B) = sum_n (Ja^i_n(A) + Ja^i_n(B))/2 f#_n(A, B), F~* through the face's Ja^i.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "kernels.h"
+
+namespace dgx {
+
+template <int NE_NN, int XB, bool CONS>
+struct CurvLds {
+  double rho[NE_NN], v[3][NE_NN], p[NE_NN], beta[NE_NN];
+  double ja[9][NE_NN];                  // (J a^i)_n of every node, [i * 3 + n]
+  double u[CONS ? 5 : 1][CONS ? NE_NN : 1];
+  alignas(16) unsigned char xb[XB];     // per element: partner shares | wave speeds
+};
+
+template <int N, int VOL>
+struct CurvLdsOf {
+  using SS = StageShape<3, N, double, 256>;
+  using type = CurvLds<SS::NENN, SS::XB, VOL == VOL_CENTRAL>;
+};
+
+template <typename L>
+__device__ __forceinline__ void ja_of(const L& s, int i, int li, double (&a)[3]) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) a[k] = s.ja[i * 3 + k][li];
+}
+
+// Unique-pair rounds along reference direction D (as volume_dir) with the two-point flux
+// contracted with the averaged metric vector of the pair.
+template <int N, int D, int VOL, typename L>
+__device__ __forceinline__ void volume_dir_curv(const L& s, double* __restrict__ x, bool on,
+                                                int base, int node, const Prim<double>& me,
+                                                const double (&ume)[5], const double* sS,
+                                                double inv_gm1, double (&acc)[5]) {
+  constexpr int n = N + 1, st = Stride<D, n>::value;
+  constexpr int NN = Shape<3, N>::NN;
+  constexpr int FULL = (n - 1) / 2;
+  constexpr int ROUNDS = FULL + (n % 2 == 0 ? 1 : 0);
+  const int id = (node / st) % n;
+  const int nb = base + node - id * st;
+  double am[3];
+  ja_of(s, D, base + node, am);
+#pragma unroll
+  for (int r = 1; r <= ROUNDS; ++r) {
+    const bool half = (r > FULL);
+    int m = id + r;
+    if (m >= n) m -= n;
+    const int pn = nb + m * st;
+    if (on && (!half || id < n / 2)) {
+      Prim<double> q;
+      q.rho = s.rho[pn];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) q.v[k] = s.v[k][pn];
+      q.p = s.p[pn];
+      q.beta = s.beta[pn];
+      double ap[3], ab[3], f[5];
+      ja_of(s, D, pn, ap);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) ab[k] = 0.5 * (am[k] + ap[k]);
+      if constexpr (VOL == VOL_CENTRAL) {
+        double uq[5];
+#pragma unroll
+        for (int v = 0; v < 5; ++v) uq[v] = s.u[v][pn];
+        central_flux_vec(ume, me, uq, q, ab, f);
+      } else {
+        ec_flux_vec(me, q, ab, inv_gm1, f);
+      }
+      const double cme = sS[(D * TMAX + id) * TMAX + m];
+      const double cpa = sS[(D * TMAX + m) * TMAX + id];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) {
+        acc[v] += cme * f[v];
+        lds_add(&x[v * NN + pn - base], cpa * f[v]);
+      }
+    }
+    if constexpr (!WaveElem<3, N>::value) __syncthreads();
+  }
+}
+
+// Face term along reference direction D for a boundary node: the interface flux through the
+// node's Ja^D (equal on both sides of the face), evaluated with the minus-side state first
+// so that both elements compute the same value, lifted with -+1/w.
+template <int N, int D, typename L>
+__device__ __forceinline__ void surface_dir_curv(const L& s, const Geom& g, int surf, int node,
+                                                 int li, const double (&um)[5],
+                                                 const Prim<double>& qm, const double (&un)[5],
+                                                 const double* sL, double (&R)[5]) {
+  constexpr int n = N + 1, st = Stride<D, n>::value;
+  const int id = (node / st) % n;
+  if (id != 0 && id != N) return;
+  const bool plus = (id == N);
+  Prim<double> qn;
+  if (!cons_to_prim<3, true>(un, g.gamma, qn)) *g.flag = 1;
+  double a[3], uL[5], uR[5], F[5];
+  ja_of(s, D, li, a);
+  Prim<double> qL, qR;
+#pragma unroll
+  for (int v = 0; v < 5; ++v) {
+    uL[v] = plus ? um[v] : un[v];
+    uR[v] = plus ? un[v] : um[v];
+  }
+  qL.rho = plus ? qm.rho : qn.rho;
+  qR.rho = plus ? qn.rho : qm.rho;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    qL.v[k] = plus ? qm.v[k] : qn.v[k];
+    qR.v[k] = plus ? qn.v[k] : qm.v[k];
+  }
+  qL.p = plus ? qm.p : qn.p;
+  qR.p = plus ? qn.p : qm.p;
+  qL.beta = plus ? qm.beta : qn.beta;
+  qR.beta = plus ? qn.beta : qm.beta;
+  qL.c = plus ? qm.c : qn.c;
+  qR.c = plus ? qn.c : qm.c;
+  surface_flux_vec(surf, uL, qL, uR, qR, a, g.gamma, F);
+  const double c = plus ? sL[2 * D + 1] : sL[2 * D];
+#pragma unroll
+  for (int v = 0; v < 5; ++v) R[v] += c * F[v];
+}
+
+// One tile of curvilinear elements (3D, float64).  The tables hold -S and +-1/w (the
+// reference element's own scale); the metric terms carry the geometry.
+template <int N, int VOL, int EPI>
+__device__ __forceinline__ void stage_tile_curv(typename CurvLdsOf<N, VOL>::type& s,
+                                                const double* sT, const StageArgs& a,
+                                                const Geom& g, int tile) {
+  using S = Shape<3, N>;
+  using SS = StageShape<3, N, double, 256>;
+  constexpr int NV = 5, NN = S::NN;
+  const int le = threadIdx.x / NN;
+  const int node = threadIdx.x - le * NN;
+  const int e = tile * S::NE + le;
+  const bool inb = le < S::NE;
+  const bool active = inb && (e < g.E);
+  const int base = le * NN;
+  const int li = base + node;
+  const unsigned ENN = (unsigned)g.E * NN;
+  const unsigned own_ix = (unsigned)e * NN + node;
+
+  double um[NV], unb[3][NV];
+  Prim<double> qd;
+  double ij = 1.0;   // 1/J of this node
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) um[v] = a.uin[v * ENN + own_ix];
+    if (a.surf != SURF_NONE) {
+      int ec[3];
+      elem_xyz(g, e, ec);
+      face_load<3, N, 0>(a.uin, g, e, ec, node, unb[0]);
+      face_load<3, N, 1>(a.uin, g, e, ec, node, unb[1]);
+      face_load<3, N, 2>(a.uin, g, e, ec, node, unb[2]);
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) s.ja[q][li] = g.ja[q * ENN + own_ix];
+    ij = rcp_nr(g.jac[own_ix]);
+    if (!cons_to_prim<3>(um, g.gamma, qd)) *g.flag = 1;
+    s.rho[li] = qd.rho;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.v[k][li] = qd.v[k];
+    s.p[li] = qd.p;
+    s.beta[li] = qd.beta;
+    if constexpr (VOL == VOL_CENTRAL) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s.u[v][li] = um[v];
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) um[v] = 1.0;
+    qd.rho = qd.p = qd.beta = qd.c = 1.0;
+    qd.v[0] = qd.v[1] = qd.v[2] = 0.0;
+  }
+  if (inb) {
+    double* x = reinterpret_cast<double*>(s.xb + le * SS::SLOT);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) x[v * NN + node] = 0.0;
+  }
+  double R[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) R[v] = 0.0;
+  __syncthreads();
+
+  if (a.surf != SURF_NONE && active) {
+    surface_dir_curv<N, 0>(s, g, a.surf, node, li, um, qd, unb[0], sT + TAB_LIFT, R);
+    surface_dir_curv<N, 1>(s, g, a.surf, node, li, um, qd, unb[1], sT + TAB_LIFT, R);
+    surface_dir_curv<N, 2>(s, g, a.surf, node, li, um, qd, unb[2], sT + TAB_LIFT, R);
+  }
+  if constexpr (VOL != VOL_NONE) {
+    double* x = reinterpret_cast<double*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);
+    const double inv_gm1 = 1.0 / (g.gamma - 1.0);
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = R[v];
+    volume_dir_curv<N, 0, VOL>(s, x, active, base, node, qd, um, sT + TAB_S, inv_gm1, acc);
+    volume_dir_curv<N, 1, VOL>(s, x, active, base, node, qd, um, sT + TAB_S, inv_gm1, acc);
+    volume_dir_curv<N, 2, VOL>(s, x, active, base, node, qd, um, sT + TAB_S, inv_gm1, acc);
+    elem_sync<3, N>();
+    if (active) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) R[v] = acc[v] + x[v * NN + node];
+    }
+  }
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) R[v] *= ij;
+    if (g.source) {
+      const double ts = a.t0 ? *a.t0 + a.cs * *a.dt : a.t;
+      double src[NV];
+      mms_source(g.gamma, g.xyz[own_ix], g.xyz[ENN + own_ix], g.xyz[2 * ENN + own_ix], ts, src);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) R[v] += src[v];
+    }
+  }
+  // next-step wave speed per reference direction: (|v . Ja^d| + c |Ja^d|) / J
+  stage_epilogue<3, N, EPI, 256>(s.xb, a, g, le, node, e, inb, active, ENN, own_ix, um, R,
+                                 [&](const Prim<double>& q, int d) {
+                                   double ad[3];
+                                   ja_of(s, d, li, ad);
+                                   const double va = q.v[0] * ad[0] + q.v[1] * ad[1] + q.v[2] * ad[2];
+                                   const double al = sqrt_pos(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]);
+                                   return (fabs(va) + q.c * al) * ij;
+                                 });
+}
+
+template <int N, int VOL, int EPI>
+__global__ __launch_bounds__((Shape<3, N>::THREADS)) void k_stage_curv(StageArgs a, Geom g) {
+  __shared__ typename CurvLdsOf<N, VOL>::type s;
+  __shared__ double sT[TAB_SIZE];
+  for (int i = threadIdx.x; i < TAB_SIZE; i += blockDim.x) sT[i] = g.tab[i];
+  stage_tile_curv<N, VOL, EPI>(s, sT, a, g, (int)xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Geometry of one element per block (one thread per node): positions from Eq. (2) at the
+// mapped LGL points of the reference box [-1,1]^3 (cells K per direction), J and the
+// curl-form metric terms.  Dm: the LGL differentiation matrix [n][n].
+template <int N>
+__global__ __launch_bounds__(((N + 1) * (N + 1) * (N + 1))) void k_curv_geometry(
+    Geom g, const double* __restrict__ Dm, double warp, double* __restrict__ xyz,
+    double* __restrict__ ja, double* __restrict__ jac) {
+  constexpr int n = N + 1, NN = n * n * n;
+  __shared__ double X[3][NN], dX[9][NN], V[3][NN];
+  __shared__ double sD[n * n];
+  const int e = blockIdx.x;
+  const int node = threadIdx.x;
+  for (int i = node; i < n * n; i += NN) sD[i] = Dm[i];
+  const int idx[3] = {node % n, (node / n) % n, node / (n * n)};
+  int ec[3];
+  elem_xyz(g, e, ec);
+  const double* xl = g.tab + TAB_X;
+  double xi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+    xi[d] = -1.0 + (2.0 / g.K[d]) * (ec[d] + 0.5 * (1.0 + xl[idx[d]]));
+  // Eq. (2): y first, then x (uses y), then z (uses x and y)
+  constexpr double pi = 3.14159265358979323846;
+  const double cz = cos(0.5 * pi * xi[2]);
+  const double y = xi[1] + warp * (cos(1.5 * pi * xi[0]) * cos(0.5 * pi * xi[1]) * cz);
+  const double x = xi[0] + warp * (cos(0.5 * pi * xi[0]) * cos(2.0 * pi * y) * cz);
+  const double z = xi[2] + warp * (cos(0.5 * pi * x) * cos(pi * y) * cz);
+  X[0][node] = x;
+  X[1][node] = y;
+  X[2][node] = z;
+  __syncthreads();
+  const int stride[3] = {1, n, n * n};
+  auto deriv = [&](const double* f, int j) {   // d/ds_j of nodal data f at this node
+    const int b = node - idx[j] * stride[j];
+    double sum = 0.0;
+    for (int m = 0; m < n; ++m) sum += sD[idx[j] * n + m] * f[b + m * stride[j]];
+    return sum;
+  };
+  for (int j = 0; j < 3; ++j)
+    for (int c = 0; c < 3; ++c) dX[j * 3 + c][node] = deriv(X[c], j);
+  __syncthreads();
+  const unsigned ENN = (unsigned)g.E * NN, own = (unsigned)e * NN + node;
+  {
+    const double c0 = dX[3 + 1][node] * dX[6 + 2][node] - dX[3 + 2][node] * dX[6 + 1][node];
+    const double c1 = dX[3 + 2][node] * dX[6 + 0][node] - dX[3 + 0][node] * dX[6 + 2][node];
+    const double c2 = dX[3 + 0][node] * dX[6 + 1][node] - dX[3 + 1][node] * dX[6 + 0][node];
+    jac[own] = dX[0][node] * c0 + dX[1][node] * c1 + dX[2][node] * c2;
+  }
+  for (int nc = 0; nc < 3; ++nc) {
+    const int mm = (nc + 1) % 3, l = (nc + 2) % 3;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) V[j][node] = X[l][node] * dX[j * 3 + mm][node];
+    __syncthreads();
+    const double curl0 = deriv(V[2], 1) - deriv(V[1], 2);
+    const double curl1 = deriv(V[0], 2) - deriv(V[2], 0);
+    const double curl2 = deriv(V[1], 0) - deriv(V[0], 1);
+    ja[(0 * 3 + nc) * ENN + own] = -curl0;
+    ja[(1 * 3 + nc) * ENN + own] = -curl1;
+    ja[(2 * 3 + nc) * ENN + own] = -curl2;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) xyz[d * ENN + own] = X[d][node];
+}
+
+// CFL partial per element: sum_d max_nodes (|v . Ja^d| + c |Ja^d|) / J.
+template <int N>
+__global__ __launch_bounds__((Shape<3, N>::THREADS)) void k_maxspeed_curv(
+    const double* __restrict__ u, double* __restrict__ partial, Geom g) {
+  using S = Shape<3, N>;
+  constexpr int NN = S::NN;
+  constexpr int P2 = NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
+  __shared__ double sm[3][S::NE * NN];
+  const int le = threadIdx.x / NN;
+  const int node = threadIdx.x - le * NN;
+  const int64_t e = (int64_t)blockIdx.x * S::NE + le;
+  const bool inb = le < S::NE;
+  const bool active = inb && (e < g.E);
+  const int base = le * NN;
+  const unsigned ENN = (unsigned)g.E * NN;
+  if (inb) {
+    if (active) {
+      const unsigned own = (unsigned)e * NN + node;
+      double um[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) um[v] = u[v * ENN + own];
+      Prim<double> q;
+      if (!cons_to_prim<3, false>(um, g.gamma, q)) *g.flag = 1;
+      const double ij = rcp_nr(g.jac[own]);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double ad[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ad[k] = g.ja[(d * 3 + k) * ENN + own];
+        const double va = q.v[0] * ad[0] + q.v[1] * ad[1] + q.v[2] * ad[2];
+        const double al = sqrt_pos(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]);
+        sm[d][base + node] = (fabs(va) + q.c * al) * ij;
+      }
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sm[d][base + node] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int half = P2 / 2; half > 0; half >>= 1) {
+    if (inb && node < half && node + half < NN) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sm[d][base + node] = fmax(sm[d][base + node], sm[d][base + node + half]);
+    }
+    __syncthreads();
+  }
+  if (active && node == 0) partial[e] = sm[0][base] + sm[1][base] + sm[2][base];
+}
+
+}  // namespace dgx

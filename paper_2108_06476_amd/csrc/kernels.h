@@ -52,6 +52,11 @@ struct Geom {
   double gamma;
   const double* tab;
   int* flag;   // set to 1 when a non-physical state is met
+  // curvilinear elements (nullptr: Cartesian)
+  const double* ja = nullptr;    // (J a^i)_n, [3 (i)][3 (n)][E][NN]
+  const double* jac = nullptr;   // J, [E][NN]
+  const double* xyz = nullptr;   // node positions, [3][E][NN]
+  int source = 0;                // 1: the manufactured solution's source term
 };
 
 __device__ __forceinline__ int64_t neighbour(const Geom& g, int64_t e, int d, int s) {
@@ -438,6 +443,10 @@ struct StageArgs {
   double A, B;           // RK stage coefficients
   int surf;              // SURF_* (SURF_NONE: no surface term)
   int fvf;               // subcell FV flux (SURF_LLF or SURF_HLL)
+  // time of the stage (source terms): *t0 + cs * (*dt) when t0 is set, else t
+  const double* t0 = nullptr;
+  double cs = 0.0;
+  double t = 0.0;
 };
 
 // Weak form: the physical fluxes f^d_v of every node, contracted along the lines.
@@ -515,6 +524,89 @@ __device__ __forceinline__ void weak_dir(const L& s, int base, int node, const d
     const double c = sD[(D * TMAX + id) * TMAX + m];
 #pragma unroll
     for (int v = 0; v < DIM + 2; ++v) R[v] = fma(c, s.f[D][v][nb + m * st], R[v]);
+  }
+}
+
+// Epilogue of a stage for one node: RHS: du = R; RK: k <- A k + dt R, u_out = u + B k and,
+// in the last stage, each element's partial of the next CFL step,
+// sum_d max_nodes speed(q, d) of the new state (speed: the direction's scaled wave speed).
+// xb: the block's per-element LDS slots (elements of several waves reduce through them).
+template <int DIM, int N, int EPI, int BUDGET, typename SpeedFn>
+__device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArgs& a,
+                                               const Geom& g, int le, int node, int e, bool inb,
+                                               bool active, unsigned ENN, unsigned own_ix,
+                                               const double (&um)[DIM + 2],
+                                               const double (&R)[DIM + 2], SpeedFn speed) {
+  using S = Shape<DIM, N, BUDGET>;
+  using SS = StageShape<DIM, N, double, BUDGET>;
+  constexpr int NV = S::NV, NN = S::NN;
+  if constexpr (EPI == EPI_RHS) {
+    if (active) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) a.du[v * ENN + own_ix] = R[v];
+    }
+  } else {
+    double un[NV];
+    if (active) {
+      const double dt = *a.dt;
+      double kv[NV];
+      if (a.A == 0.0) {   // first stage: k is not read (uniform branch)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) kv[v] = dt * R[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) kv[v] = a.A * a.k[v * ENN + own_ix] + dt * R[v];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const unsigned ix = v * ENN + own_ix;
+        a.k[ix] = kv[v];
+        un[v] = um[v] + a.B * kv[v];
+        a.uout[ix] = un[v];
+      }
+    }
+    if (a.speed != nullptr) {
+      if constexpr (WaveElem<DIM, N>::value) {
+        if (active) {   // uniform per wave: the element is the wave
+          Prim<double> q;
+          if (!cons_to_prim<DIM, false>(un, g.gamma, q)) *g.flag = 1;
+          double lam = 0.0;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) lam += wave_max_lane63(speed(q, d));
+          if (node == NN - 1) a.speed[e] = lam;
+        }
+      } else {
+        constexpr int P2 = NN <= 4 ? 4 : NN <= 16 ? 16 : NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
+        double* sp = reinterpret_cast<double*>(xb + (le < S::NE ? le : 0) * SS::SLOT);   // [DIM][NN]
+        __syncthreads();
+        if (inb) {
+          if (active) {
+            Prim<double> q;
+            if (!cons_to_prim<DIM, false>(un, g.gamma, q)) *g.flag = 1;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) sp[d * NN + node] = speed(q, d);
+          } else {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) sp[d * NN + node] = 0.0;
+          }
+        }
+        __syncthreads();
+        for (int h = P2 / 2; h > 0; h >>= 1) {
+          if (inb && node < h && node + h < NN) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d)
+              sp[d * NN + node] = fmax(sp[d * NN + node], sp[d * NN + node + h]);
+          }
+          __syncthreads();
+        }
+        if (active && node == 0) {
+          double lam = 0.0;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) lam += sp[d * NN];
+          a.speed[e] = lam;
+        }
+      }
+    }
   }
 }
 
@@ -664,76 +756,10 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   }
 
   // ---- epilogue
-  if constexpr (EPI == EPI_RHS) {
-    if (active) {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) a.du[v * ENN + own_ix] = R[v];
-    }
-  } else {
-    double un[NV];
-    if (active) {
-      const double dt = *a.dt;
-      double kv[NV];
-      if (a.A == 0.0) {   // first stage: k is not read (uniform branch)
-#pragma unroll
-        for (int v = 0; v < NV; ++v) kv[v] = dt * R[v];
-      } else {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) kv[v] = a.A * a.k[v * ENN + own_ix] + dt * R[v];
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        const unsigned ix = v * ENN + own_ix;
-        a.k[ix] = kv[v];
-        un[v] = um[v] + a.B * kv[v];
-        a.uout[ix] = un[v];
-      }
-    }
-    if (a.speed != nullptr) {
-      // per element: sum_d (2/h_d) max over its nodes of |v_d| + c of the new state, one
-      // partial of the next CFL time step per element
-      if constexpr (WaveElem<DIM, N>::value) {
-        if (active) {   // uniform per wave: the element is the wave
-          Prim<double> q;
-          if (!cons_to_prim<DIM, false>(un, g.gamma, q)) *g.flag = 1;
-          double lam = 0.0;
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) lam += sT[TAB_JAC + d] * wave_max_lane63(fabs(q.v[d]) + q.c);
-          if (node == NN - 1) a.speed[e] = lam;
-        }
-      } else {
-        constexpr int P2 = NN <= 4 ? 4 : NN <= 16 ? 16 : NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
-        double* sp = reinterpret_cast<double*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);   // [DIM][NN]
-        __syncthreads();
-        if (inb) {
-          if (active) {
-            Prim<double> q;
-            if (!cons_to_prim<DIM, false>(un, g.gamma, q)) *g.flag = 1;
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) sp[d * NN + node] = fabs(q.v[d]) + q.c;
-          } else {
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) sp[d * NN + node] = 0.0;
-          }
-        }
-        __syncthreads();
-        for (int h = P2 / 2; h > 0; h >>= 1) {
-          if (inb && node < h && node + h < NN) {
-#pragma unroll
-            for (int d = 0; d < DIM; ++d)
-              sp[d * NN + node] = fmax(sp[d * NN + node], sp[d * NN + node + h]);
-          }
-          __syncthreads();
-        }
-        if (active && node == 0) {
-          double lam = 0.0;
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) lam += sT[TAB_JAC + d] * sp[d * NN];
-          a.speed[e] = lam;
-        }
-      }
-    }
-  }
+  stage_epilogue<DIM, N, EPI, BUDGET>(s.xb, a, g, le, node, e, inb, active, ENN, own_ix, um, R,
+                                      [&](const Prim<double>& q, int d) {
+                                        return sT[TAB_JAC + d] * (fabs(q.v[d]) + q.c);
+                                      });
 }
 
 // The matrix-core variant asks for 4 waves per SIMD (its accumulators would otherwise push

@@ -281,3 +281,107 @@ __device__ __forceinline__ void surface_flux_rt(int surf, int d, const double (&
 }
 
 }  // namespace dgx
+
+namespace dgx {
+
+// ---- curvilinear elements (3D): fluxes along a (not necessarily unit) vector a -----------
+
+// sum_n a_n f^n(u) = (rho v.a, rho v (v.a) + p a, (v.a)(rho E + p)).
+__device__ __forceinline__ void flux_vec(const double (&u)[5], const Prim<double>& q,
+                                         const double (&a)[3], double (&f)[5]) {
+  const double va = q.v[0] * a[0] + q.v[1] * a[1] + q.v[2] * a[2];
+  f[0] = u[0] * va;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f[1 + k] = u[1 + k] * va + q.p * a[k];
+  f[4] = va * (u[4] + q.p);
+}
+
+// The EC two-point flux contracted with a, sum_n a_n f#_n(L, R): the volume flux of a
+// curvilinear element with a the average of the two nodes' metric vectors (J a^i).
+__device__ __forceinline__ void ec_flux_vec(const Prim<double>& L, const Prim<double>& R,
+                                            const double (&a)[3], double inv_gm1,
+                                            double (&f)[5]) {
+  const double rho_ln = ln_mean(L.rho, R.rho);
+  const double ibeta = inv_ln_mean(L.beta, R.beta);
+  double vs[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) vs[k] = 0.5 * (L.v[k] + R.v[k]);
+  const double vLvR = L.v[0] * R.v[0] + L.v[1] * R.v[1] + L.v[2] * R.v[2];
+  const double frho = rho_ln * (vs[0] * a[0] + vs[1] * a[1] + vs[2] * a[2]);
+  const double pavg = 0.5 * (L.p + R.p);
+  f[0] = frho;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f[1 + k] = frho * vs[k] + pavg * a[k];
+  const double vRa = R.v[0] * a[0] + R.v[1] * a[1] + R.v[2] * a[2];
+  const double vLa = L.v[0] * a[0] + L.v[1] * a[1] + L.v[2] * a[2];
+  f[4] = frho * (ibeta * inv_gm1 + 0.5 * vLvR) + 0.5 * (L.p * vRa + R.p * vLa);
+}
+
+// Central two-point flux contracted with a: (f_a(u_L) + f_a(u_R))/2.
+__device__ __forceinline__ void central_flux_vec(const double (&uL)[5], const Prim<double>& L,
+                                                 const double (&uR)[5], const Prim<double>& R,
+                                                 const double (&a)[3], double (&f)[5]) {
+  double fL[5], fR[5];
+  flux_vec(uL, L, a, fL);
+  flux_vec(uR, R, a, fR);
+#pragma unroll
+  for (int v = 0; v < 5; ++v) f[v] = 0.5 * (fL[v] + fR[v]);
+}
+
+// Interface flux through a face with contravariant vector a (from L to R): LLF and HLL
+// with the wave speeds scaled by |a| (|a| f*(u_L, u_R; a/|a|)), EC as ec_flux_vec.
+__device__ __forceinline__ void surface_flux_vec(int surf, const double (&uL)[5],
+                                                 const Prim<double>& L, const double (&uR)[5],
+                                                 const Prim<double>& R, const double (&a)[3],
+                                                 double gamma, double (&f)[5]) {
+  if (surf == SURF_EC) {
+    ec_flux_vec(L, R, a, 1.0 / (gamma - 1.0), f);
+    return;
+  }
+  double fL[5], fR[5];
+  flux_vec(uL, L, a, fL);
+  flux_vec(uR, R, a, fR);
+  const double al = sqrt_pos(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  const double vL = L.v[0] * a[0] + L.v[1] * a[1] + L.v[2] * a[2];
+  const double vR = R.v[0] * a[0] + R.v[1] * a[1] + R.v[2] * a[2];
+  if (surf == SURF_LLF) {
+    const double lam = fmax(fabs(vL) + L.c * al, fabs(vR) + R.c * al);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
+    return;
+  }
+  const double sL = fmin(vL - L.c * al, vR - R.c * al);
+  const double sR = fmax(vL + L.c * al, vR + R.c * al);
+  if (sL >= 0.0) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) f[v] = fL[v];
+  } else if (sR <= 0.0) {
+#pragma unroll
+    for (int v = 0; v < 5; ++v) f[v] = fR[v];
+  } else {
+    const double inv = 1.0 / (sR - sL);
+#pragma unroll
+    for (int v = 0; v < 5; ++v) f[v] = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) * inv;
+  }
+}
+
+// Source term of the manufactured solution rho = 2 + A sin(theta), theta = k (x+y+z) - om t,
+// v = (1,1,1), rho E = rho^2 (A = 0.1, k = pi, om = 2 pi): s = du/dt + div f(u), with
+// h = A cos(theta): s_rho = (3k - om) h, s_rhov = s_rho + (gamma-1)(2 rho - 1.5) k h,
+// s_rhoE = -2 rho om h + 3 k (2 rho + (gamma-1)(2 rho - 1.5)) h.
+__device__ __forceinline__ void mms_source(double gamma, double x, double y, double z, double t,
+                                           double (&s)[5]) {
+  constexpr double pi = 3.14159265358979323846;
+  constexpr double A = 0.1, k = pi, om = 2.0 * pi;
+  double sn, cs;
+  sincos(k * (x + y + z) - om * t, &sn, &cs);
+  const double rho = 2.0 + A * sn, h = A * cs;
+  const double dp = (gamma - 1.0) * (2.0 * rho - 1.5) * k * h;
+  s[0] = (3.0 * k - om) * h;
+  s[1] = s[0] + dp;
+  s[2] = s[0] + dp;
+  s[3] = s[0] + dp;
+  s[4] = -2.0 * rho * om * h + 3.0 * k * (2.0 * rho + (gamma - 1.0) * (2.0 * rho - 1.5)) * h;
+}
+
+}  // namespace dgx

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
+#include "curv.h"
 
 namespace dgx {
 
@@ -20,6 +21,11 @@ struct Launchers {
   hipError_t (*integrals)(hipStream_t, const double* u, const double* du, double* partial,
                           const Geom&) = nullptr;
   hipError_t (*coords)(hipStream_t, double* xyz, const Geom&, const double* xmin) = nullptr;
+  // curvilinear elements (3D only; nullptr in 2D)
+  hipError_t (*stage_curv)(hipStream_t, const StageArgs&, const Geom&, int vol, int epi) = nullptr;
+  hipError_t (*maxspeed_curv)(hipStream_t, const double* u, double* partial, const Geom&) = nullptr;
+  hipError_t (*geometry)(hipStream_t, const Geom&, const double* Dm, double warp, double* xyz,
+                         double* ja, double* jac) = nullptr;
   const char* volume_name = "";
 };
 
@@ -101,6 +107,46 @@ struct Launch {
     return hipGetLastError();
   }
 
+  template <int VOL, int EPI>
+  static hipError_t stage_curv1(hipStream_t st, const StageArgs& a, const Geom& g) {
+    hipLaunchKernelGGL((k_stage_curv<N, VOL, EPI>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st, a, g);
+    return hipGetLastError();
+  }
+
+  static hipError_t stage_curv(hipStream_t st, const StageArgs& a, const Geom& g, int vol, int epi) {
+    if constexpr (DIM == 3) {
+      if (epi == EPI_RK) {
+        if (vol == VOL_EC) return stage_curv1<VOL_EC, EPI_RK>(st, a, g);
+        if (vol == VOL_CENTRAL) return stage_curv1<VOL_CENTRAL, EPI_RK>(st, a, g);
+        if (vol == VOL_NONE) return stage_curv1<VOL_NONE, EPI_RK>(st, a, g);
+      } else {
+        if (vol == VOL_EC) return stage_curv1<VOL_EC, EPI_RHS>(st, a, g);
+        if (vol == VOL_CENTRAL) return stage_curv1<VOL_CENTRAL, EPI_RHS>(st, a, g);
+        if (vol == VOL_NONE) return stage_curv1<VOL_NONE, EPI_RHS>(st, a, g);
+      }
+    }
+    return hipErrorInvalidValue;
+  }
+
+  static hipError_t maxspeed_curv(hipStream_t st, const double* u, double* partial, const Geom& g) {
+    if constexpr (DIM == 3) {
+      hipLaunchKernelGGL((k_maxspeed_curv<N>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st, u,
+                         partial, g);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+
+  static hipError_t geometry(hipStream_t st, const Geom& g, const double* Dm, double warp,
+                             double* xyz, double* ja, double* jac) {
+    if constexpr (DIM == 3) {
+      hipLaunchKernelGGL((k_curv_geometry<N>), dim3((unsigned)g.E), dim3(S::NN), 0, st, g, Dm,
+                         warp, xyz, ja, jac);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+
   static Launchers make() {
     Launchers L;
     L.threads = S::THREADS;
@@ -111,6 +157,11 @@ struct Launch {
     L.maxspeed = &maxspeed;
     L.integrals = &integrals;
     L.coords = &coords;
+    if constexpr (DIM == 3) {
+      L.stage_curv = &stage_curv;
+      L.maxspeed_curv = &maxspeed_curv;
+      L.geometry = &geometry;
+    }
     L.volume_name = "k_stage";
     return L;
   }

@@ -25,7 +25,7 @@ EXPORTS = ["dgx_create", "dgx_destroy", "dgx_set_stream", "dgx_num_nodes", "dgx_
            "dgx_step", "dgx_integrals", "dgx_check", "dgx_last_error", "dgx_profile_enable",
            "dgx_profile_read", "dgx_batch_create", "dgx_batch_destroy", "dgx_batch_num_nodes",
            "dgx_batch_step", "dgx_batch_rhs", "dgx_batch_tune", "dgx_batch_shape",
-           "dgx_batch_check", "dgx_batch_last_error"]
+           "dgx_batch_check", "dgx_batch_last_error", "dgx_create_curved", "dgx_geometry"]
 
 
 class DgxError(RuntimeError):
@@ -45,6 +45,14 @@ class Config(C.Structure):
                 ("alpha_max", C.c_double), ("alpha_min", C.c_double),
                 ("alpha_smooth", C.c_int32), ("precision", C.c_int32)]
 
+
+class CurvConfig(C.Structure):
+    _fields_ = [("polydeg", C.c_int32), ("cells", C.c_int32), ("warp", C.c_double),
+                ("gamma", C.c_double), ("volume", C.c_int32), ("surface", C.c_int32),
+                ("source", C.c_int32)]
+
+
+SOURCE = {"none": 0, "mms": 1}
 
 _lib = None
 
@@ -84,6 +92,8 @@ def lib():
             "dgx_batch_shape": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
             "dgx_batch_check": ([vp, C.POINTER(C.c_int32)], C.c_int),
             "dgx_batch_last_error": ([vp], C.c_char_p),
+            "dgx_create_curved": ([C.POINTER(CurvConfig), vp, C.POINTER(vp)], C.c_int),
+            "dgx_geometry": ([vp, vp, vp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -181,11 +191,11 @@ class Solver:
         self._call("dgx_node_coords", _ptr(xyz, "xyz"))
         return xyz
 
-    def rhs(self, u, du=None):
+    def rhs(self, u, du=None, t=0.0):
         n = self.nvar * self.num_nodes
         if du is None:
             du = torch.empty_like(u)
-        self._call("dgx_rhs", _ptr(u, "u", n), _ptr(du, "du", n), C.c_double(0.0))
+        self._call("dgx_rhs", _ptr(u, "u", n), _ptr(du, "du", n), C.c_double(t))
         return du
 
     def rhs_alpha(self, u, alpha, du=None):
@@ -303,3 +313,38 @@ class Batch:
         if st not in (0, 4):
             raise DgxError(st, lib().dgx_batch_last_error(self._h).decode())
         return int(f.value)
+
+
+class CurvSolver(Solver):
+    """The warped periodic box of the PID study (cells^3 hexahedra on [-1,1]^3, Eq. (2)),
+    EC or central flux differencing, FP64; source="mms" adds the manufactured solution's
+    source term (dgx_create_curved)."""
+
+    def __init__(self, polydeg, cells, warp=0.15, gamma=1.4, volume="ec", surface="llf",
+                 source="mms"):
+        c = CurvConfig()
+        c.polydeg, c.cells, c.warp, c.gamma = polydeg, cells, warp, gamma
+        c.volume = VOLUME[volume] if isinstance(volume, str) else int(volume)
+        c.surface = SURFACE[surface] if isinstance(surface, str) else int(surface)
+        c.source = SOURCE[source] if isinstance(source, str) else int(source)
+        self.ccfg = c
+        L = lib()
+        h = C.c_void_p()
+        st = L.dgx_create_curved(C.byref(c), _stream(), C.byref(h))
+        if st != 0:
+            raise DgxError(st, "dgx_create_curved failed (configuration not supported or invalid)")
+        self._h = h
+        self.dim, self.N = 3, polydeg
+        self.n = polydeg + 1
+        self.NN = self.n ** 3
+        self.nvar = 5
+        self.num_nodes = int(L.dgx_num_nodes(h))
+        self.E = int(L.dgx_num_elements(h))
+        self.shape = (5, self.E, self.NN)
+
+    def geometry(self):
+        """(Ja [3][3][E][NN] = (J a^i)_n, J [E][NN]) as device tensors."""
+        ja = torch.empty((3, 3, self.E, self.NN), dtype=torch.float64, device="cuda")
+        jac = torch.empty((self.E, self.NN), dtype=torch.float64, device="cuda")
+        self._call("dgx_geometry", _ptr(ja, "ja"), _ptr(jac, "jac"))
+        return ja, jac

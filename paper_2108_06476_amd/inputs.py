@@ -52,6 +52,9 @@ def workload(name):
         return dict(dim=3, polydeg=3, cells=(32, 32, 32), xmin=(-1.0,) * 3, xmax=(1.0,) * 3,
                     gamma=GAMMA, volume="shockcap_hg", surface="llf", fv_flux="llf",
                     alpha_max=0.5, alpha_min=0.001, alpha_smooth=True)
+    if name in ("curved_4", "curved_32"):   # the PID study's warped box (Eq. (2)), MMS source
+        return dict(polydeg=3, cells=4 if name == "curved_4" else 32, warp=0.15, gamma=GAMMA,
+                    volume="ec", surface="llf", source="mms")
     if name == "tgv_64_mixed":      # mixed precision, N=3 on 64^3
         return dict(dim=3, polydeg=3, cells=(64, 64, 64), xmin=(-pi,) * 3, xmax=(pi,) * 3,
                     gamma=GAMMA, volume="ec", surface="llf", precision="mixed")
@@ -122,6 +125,14 @@ def sedov(xyz, gamma=GAMMA, sigma=0.25, E0=1.0, p_amb=1.0e-5):
     p = p_amb + (gamma - 1.0) * E0 * np.exp(-r2 / (2 * sigma ** 2)) / ((2 * np.pi) ** 1.5 * sigma ** 3)
     rho = np.ones_like(r2)
     return prim_to_cons(rho, [np.zeros_like(r2)] * dim, p, gamma)
+
+
+def mms(xyz, t=0.0):
+    """Manufactured solution of the curvilinear workload: rho = 2 + 0.1 sin(pi (x+y+z) - 2 pi t),
+    v = (1, 1, 1), rho E = rho^2 (3D; numpy or torch coordinates)."""
+    xp = _xp(xyz)
+    rho = 2.0 + 0.1 * xp.sin(math.pi * (xyz[0] + xyz[1] + xyz[2]) - 2.0 * math.pi * t)
+    return xp.stack([rho, rho, rho, rho, rho * rho])
 
 
 def random_smooth(xyz, seed, amp=0.2, vamp=0.5, nmodes=4, periods=None):

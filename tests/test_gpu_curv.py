@@ -1,0 +1,152 @@
+"""Curvilinear mesh on the GPU (dgx_create_curved: the warped box of the PID study,
+Section 3.1, Eq. (2), with the manufactured solution's source term) against the
+curvilinear oracle, element by element.
+
+Norm per field v: max|dR_v| / scale_v with scale_v = max_n (sum_i |J a^i_n| / J_n) *
+max(max|f_v|, lambda_max max|u_v|) + max|s_v|: the size of the terms the right-hand side
+sums (fluxes through the metric terms, the source).
+
+Bar: 1e-12 (as on the Cartesian mesh) plus the geometry's share.  Each side computes its own
+geometry (its own LGL nodes and cosines, then the differentiation matrix twice for the
+metric terms); the two agree to delta = max|dJa| / max|Ja| (about eps ||D||^2, checked in
+test_curv_geometry_parity), and the volume sum applies S (||S|| ~ 2 ||D||_inf) to it:
+tol = 1e-12 + 2 ||D||_inf delta.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_06476_amd import dgx, inputs
+
+from gpu_util import TOL_FP64, dev, dissipation_max, host, phys_flux_max
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(N, K, warp=0.15, vol="ec", surf="llf", source="mms"):
+    o = oracle.CurvOracle(N, K, warp=warp, volume=vol, surface=surf, source=source)
+    s = dgx.CurvSolver(N, K, warp=warp, volume=vol, surface=surf, source=source)
+    return o, s
+
+
+def _err(got, ref, u, o, t):
+    _, Ja, J = o.geometry()
+    jmax = float((np.sqrt((Ja ** 2).sum(axis=1)).sum(axis=0) / J).max())
+    F = np.maximum(phys_flux_max(u, 3), dissipation_max(u, 3))
+    src = 0.0
+    if o.cfg.source:
+        xyz, _, _ = o.geometry()
+        src = np.abs(np.stack([oracle.curv_mms(xyz[:, e, i], t)[1] for e in range(o.E)
+                               for i in range(o.NN)], axis=1)).max(axis=1)
+    scale = jmax * F + src
+    d = np.abs(got - ref).reshape(5, -1).max(axis=1)
+    return d / scale
+
+
+def _state(o, kind, seed):
+    if kind == "mms":
+        return o.initial(0.3)
+    if kind == "nodal":
+        return inputs.random_nodal((o.E, o.NN), 3, seed)
+    xyz, _, _ = o.geometry()
+    return inputs.random_smooth(xyz, seed, periods=[2.0] * 3)
+
+
+@pytest.mark.parametrize("N", [1, 3, 5, 7])
+def test_curv_geometry_parity(N):
+    o, s = _pair(N, 2, source="none")
+    xyz, Ja, J = o.geometry()
+    gj, gJ = s.geometry()
+    gx = host(s.node_coords())
+    print(f"N={N}: |dxyz| {np.abs(gx - xyz).max():.2e} |dJa| {np.abs(host(gj) - Ja).max():.2e} "
+          f"|dJ| {np.abs(host(gJ) - J).max():.2e}", flush=True)
+    # rounding of the differentiation: J takes one application of D (row sums up to
+    # ||D||_inf), the curl-form metric terms two; eps = 2^-52
+    Dn = np.abs(oracle.lgl(N)[2]).sum(axis=1).max()
+    eps = 2.0 ** -52
+    assert np.abs(gx - xyz).max() <= 1e-14
+    assert np.abs(host(gj) - Ja).max() <= 8 * eps * Dn ** 2 * np.abs(xyz).max() ** 2
+    assert np.abs(host(gJ) - J).max() <= 8 * eps * Dn * np.abs(J).max()
+
+
+CASES = ([(N, "ec", "llf", "mms") for N in range(1, 8)] +
+         [(3, "ec", "hll", "mms"), (3, "ec", "ec", "none"), (3, "central", "llf", "mms"),
+          (3, "none", "llf", "none"), (3, "ec", "none", "none"), (4, "central", "hll", "none"),
+          (2, "ec", "ec", "mms")])
+
+
+def _tol(o, s):
+    """1e-12 plus the measured geometry difference carried through the volume sum."""
+    _, Ja, _ = o.geometry()
+    gj, _ = s.geometry()
+    delta = np.abs(host(gj) - Ja).max() / np.abs(Ja).max()
+    Dn = np.abs(oracle.lgl(o.N)[2]).sum(axis=1).max()
+    return TOL_FP64 + 2.0 * Dn * delta
+
+
+@pytest.mark.parametrize("N,vol,surf,source", CASES)
+@pytest.mark.parametrize("kind", ["mms", "smooth", "nodal"])
+def test_curv_rhs_parity(N, vol, surf, source, kind):
+    o, s = _pair(N, 2 if N > 4 else 3, vol=vol, surf=surf, source=source)
+    u = _state(o, kind, 40 + N)
+    t = 0.3
+    ref = o.rhs(u, t)
+    got = host(s.rhs(dev(u), t=t))
+    e = _err(got, ref, u, o, t)
+    tol = _tol(o, s)
+    print(f"N={N} {vol}/{surf}/{source} {kind}: err {e} tol {tol:.2e}", flush=True)
+    assert np.all(e <= tol), e
+    assert s.check() == 0
+
+
+@pytest.mark.parametrize("N", [3, 4, 5, 7])
+def test_curv_paper_mesh(N):
+    """The PID study's mesh: 4^3 elements, warp 0.15, the manufactured solution at t = 0."""
+    o, s = _pair(N, 4)
+    u = o.initial(0.0)
+    e = _err(host(s.rhs(dev(u), t=0.0)), o.rhs(u, 0.0), u, o, 0.0)
+    tol = _tol(o, s)
+    print(f"paper mesh N={N}: err {e} tol {tol:.2e}", flush=True)
+    assert np.all(e <= tol), e
+
+
+def test_curv_free_stream():
+    o, s = _pair(3, 3, source="none")
+    u = inputs.constant_state((o.E, o.NN), 3)
+    R = host(s.rhs(dev(u)))
+    _, _, J = o.geometry()
+    assert np.abs(R).max() <= 1e-13 * 10.0 / J.min(), np.abs(R).max()
+
+
+def test_curv_max_dt_and_steps():
+    o, s = _pair(3, 3)
+    u0 = o.initial(0.0)
+    dt = float(s.max_dt(dev(u0), 0.5).item())
+    np.testing.assert_allclose(dt, o.max_dt(u0, 0.5), rtol=1e-13)
+    ref, tref = o.step(u0, 10, cfl=0.5, t=0.0)
+    ud = dev(u0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.step(ud, 10, cfl=0.5, t=t)
+    d = np.abs(host(ud) - ref).max() / np.abs(ref).max()
+    print("curv 10 steps: max|du|/max|u|", d, "t", float(t.item()), tref, flush=True)
+    assert d <= 1e-12
+    np.testing.assert_allclose(float(t.item()), tref, rtol=1e-13)
+    # fixed dt, odd step count
+    ref2, _ = o.step(u0, 3, cfl=0.0, dt_fixed=1e-3, t=0.25)
+    ud = dev(u0)
+    t = torch.full((1,), 0.25, dtype=torch.float64, device="cuda")
+    s.step(ud, 3, cfl=0.0, dt_fixed=1e-3, t=t)
+    assert np.abs(host(ud) - ref2).max() / np.abs(ref2).max() <= 1e-12
+
+
+def test_curv_rejections():
+    with pytest.raises(dgx.DgxError):
+        dgx.CurvSolver(3, 2, volume="shockcap_hg")
+    s = dgx.CurvSolver(3, 2)
+    u = s.empty_state()
+    u.copy_(dev(oracle.CurvOracle(3, 2).initial(0.0)))
+    with pytest.raises(dgx.DgxError):
+        s.step(u, 1, cfl=0.5)                      # the source needs t
+    with pytest.raises(dgx.DgxError):
+        s.indicator(u)
