@@ -1198,3 +1198,279 @@ int orc_curv_step(const orc_curv_config *cfg, double *u, int32_t nsteps, double 
   curv_free(&c);
   return st;
 }
+
+/* ========================================================================= */
+/* Ideal MHD (the PID study's second system, Section 3.1): weak-form DGSEM     */
+/* with the HLL interface flux on the periodic Cartesian box, 8 variables      */
+/* u = (rho, rho v, E, B), mu_0 = 1, no divergence cleaning.                   */
+/* ========================================================================= */
+
+typedef struct { double rho, v[3], p, B[3], pt, c2, b2; } mhd_prim_t;
+
+/* p = (gamma-1)(E - rho |v|^2/2 - |B|^2/2), total pressure pt = p + |B|^2/2. */
+static int mhd_to_prim(const double *u, double gamma, mhd_prim_t *q)
+{
+  q->rho = u[0];
+  double v2 = 0.0, B2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    q->v[k] = u[1 + k] / u[0];
+    q->B[k] = u[5 + k];
+    v2 = v2 + q->v[k] * q->v[k];
+    B2 = B2 + q->B[k] * q->B[k];
+  }
+  q->p = (gamma - 1.0) * (u[4] - 0.5 * u[0] * v2 - 0.5 * B2);
+  q->pt = q->p + 0.5 * B2;
+  q->c2 = gamma * q->p / q->rho;   /* sound speed squared */
+  q->b2 = B2 / q->rho;             /* Alfven speed squared (|B|^2 / rho) */
+  if (!(q->rho > 0.0) || !(q->p > 0.0) || !isfinite(q->rho) || !isfinite(q->p)) return 1;
+  return 0;
+}
+
+/* f^d(u) = (rho v_d, rho v_d v + pt e_d - B_d B, v_d (E + pt) - B_d (v.B), v_d B - B_d v). */
+static void mhd_flux(const double *u, const mhd_prim_t *q, int d, double *f)
+{
+  const double vB = q->v[0] * q->B[0] + q->v[1] * q->B[1] + q->v[2] * q->B[2];
+  f[0] = u[1 + d];
+  for (int k = 0; k < 3; ++k) f[1 + k] = u[1 + d] * q->v[k] + (k == d ? q->pt : 0.0) - q->B[d] * q->B[k];
+  f[4] = q->v[d] * (u[4] + q->pt) - q->B[d] * vB;
+  for (int k = 0; k < 3; ++k) f[5 + k] = q->v[d] * q->B[k] - q->B[d] * q->v[k];
+}
+
+/* fast magnetosonic speed along d: c_f^2 = (a^2 + b^2 + sqrt((a^2 + b^2)^2 - 4 a^2 b_d^2))/2
+ * with a^2 = gamma p / rho, b^2 = |B|^2 / rho, b_d^2 = B_d^2 / rho. */
+static double mhd_cf(const mhd_prim_t *q, int d)
+{
+  const double s = q->c2 + q->b2, bd2 = q->B[d] * q->B[d] / q->rho;
+  double disc = s * s - 4.0 * q->c2 * bd2;
+  if (disc < 0.0) disc = 0.0;
+  return sqrt(0.5 * (s + sqrt(disc)));
+}
+
+/* HLL with s_L = min(v_dL - c_fL, v_dR - c_fR), s_R = max(v_dL + c_fL, v_dR + c_fR). */
+static void mhd_hll(const double *uL, const mhd_prim_t *L, const double *uR, const mhd_prim_t *R,
+                    int d, double *f)
+{
+  double fL[8], fR[8];
+  mhd_flux(uL, L, d, fL);
+  mhd_flux(uR, R, d, fR);
+  const double cL = mhd_cf(L, d), cR = mhd_cf(R, d);
+  double a = L->v[d] - cL, b = R->v[d] - cR;
+  const double sL = a < b ? a : b;
+  a = L->v[d] + cL; b = R->v[d] + cR;
+  const double sR = a > b ? a : b;
+  for (int v = 0; v < 8; ++v) {
+    if (sL >= 0.0) f[v] = fL[v];
+    else if (sR <= 0.0) f[v] = fR[v];
+    else f[v] = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) / (sR - sL);
+  }
+}
+
+/* LLF with lambda = max(|v_dL| + c_fL, |v_dR| + c_fR). */
+static void mhd_llf(const double *uL, const mhd_prim_t *L, const double *uR, const mhd_prim_t *R,
+                    int d, double *f)
+{
+  double fL[8], fR[8];
+  mhd_flux(uL, L, d, fL);
+  mhd_flux(uR, R, d, fR);
+  const double lL = fabs(L->v[d]) + mhd_cf(L, d), lR = fabs(R->v[d]) + mhd_cf(R, d);
+  const double lam = lL > lR ? lL : lR;
+  for (int v = 0; v < 8; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
+}
+
+int orc_mhd_flux(const double *u, int d, double gamma, double *f)
+{
+  mhd_prim_t q;
+  int bad = mhd_to_prim(u, gamma, &q);
+  mhd_flux(u, &q, d, f);
+  return bad ? ORC_ENONPHYS : ORC_OK;
+}
+
+int orc_mhd_surface_flux(int kind, const double *uL, const double *uR, int d, double gamma,
+                         double *f)
+{
+  mhd_prim_t L, R;
+  int bad = mhd_to_prim(uL, gamma, &L) | mhd_to_prim(uR, gamma, &R);
+  if (kind == ORC_SURF_HLL) mhd_hll(uL, &L, uR, &R, d, f);
+  else mhd_llf(uL, &L, uR, &R, d, f);
+  return bad ? ORC_ENONPHYS : ORC_OK;
+}
+
+double orc_mhd_fast_speed(const double *u, int d, double gamma)
+{
+  mhd_prim_t q;
+  mhd_to_prim(u, gamma, &q);
+  return mhd_cf(&q, d);
+}
+
+static int mhd_setup(const orc_mhd_config *cfg, mesh_t *m)
+{
+  if (!cfg || cfg->cells < 1) return ORC_EINVAL;
+  if (cfg->surface != ORC_SURF_HLL && cfg->surface != ORC_SURF_LLF) return ORC_EINVAL;
+  orc_config q;
+  memset(&q, 0, sizeof(q));
+  q.dim = 3;
+  q.polydeg = cfg->polydeg;
+  for (int d = 0; d < 3; ++d) {
+    q.cells[d] = cfg->cells;
+    q.xmin[d] = -1.0;
+    q.xmax[d] = 1.0;
+  }
+  q.gamma = cfg->gamma;
+  return setup(&q, m);
+}
+
+int64_t orc_mhd_num_nodes(const orc_mhd_config *cfg)
+{
+  mesh_t m;
+  if (mhd_setup(cfg, &m)) return -1;
+  return m.E * m.NN;
+}
+
+/* Weak form: du = (2/h) sum_d [ sum_m Dhat_{i_d m} f^d(u_m)
+ *                              - ([i_d == N] f*_{d+} - [i_d == 0] f*_{d-}) / w_0 ],
+ * u laid out [8][E][NN] on the Cartesian box [-1,1]^3 (cells^3 elements). */
+int orc_mhd_rhs(const orc_mhd_config *cfg, const double *u, double *du)
+{
+  mesh_t m;
+  int st = mhd_setup(cfg, &m);
+  if (st) return st;
+  const int n = m.n, N = m.N, NN = m.NN;
+  const double gamma = cfg->gamma;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(| : bad)
+  for (int64_t e = 0; e < m.E; ++e) {
+    double ue[NMAX * NMAX * NMAX][8];
+    mhd_prim_t qe[NMAX * NMAX * NMAX];
+    for (int node = 0; node < NN; ++node) {
+      for (int v = 0; v < 8; ++v) ue[node][v] = u[((int64_t)v * m.E + e) * NN + node];
+      bad |= mhd_to_prim(ue[node], gamma, &qe[node]);
+    }
+    for (int node = 0; node < NN; ++node) {
+      int idx[3];
+      node_idx(&m, node, idx);
+      double R[8] = {0, 0, 0, 0, 0, 0, 0, 0}, f[8];
+      for (int d = 0; d < 3; ++d) {
+        const int id = idx[d];
+        double V[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int mm = 0; mm < n; ++mm) {
+          int pidx[3] = {idx[0], idx[1], idx[2]};
+          pidx[d] = mm;
+          const int pn = node_of(&m, pidx);
+          mhd_flux(ue[pn], &qe[pn], d, f);
+          for (int v = 0; v < 8; ++v) V[v] = V[v] + m.Dhat[id * n + mm] * f[v];
+        }
+        double Sf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (id == N || id == 0) {
+          int pidx[3] = {idx[0], idx[1], idx[2]};
+          pidx[d] = (id == N) ? 0 : N;
+          const int64_t nb = neighbour(&m, e, d, id == N ? +1 : -1);
+          const int pn = node_of(&m, pidx);
+          double un[8];
+          mhd_prim_t qn;
+          for (int v = 0; v < 8; ++v) un[v] = u[((int64_t)v * m.E + nb) * NN + pn];
+          bad |= mhd_to_prim(un, gamma, &qn);
+          if (id == N) {
+            if (cfg->surface == ORC_SURF_HLL) mhd_hll(ue[node], &qe[node], un, &qn, d, f);
+            else mhd_llf(ue[node], &qe[node], un, &qn, d, f);
+            for (int v = 0; v < 8; ++v) Sf[v] = Sf[v] + f[v] / m.w[N];
+          }
+          if (id == 0) {
+            if (cfg->surface == ORC_SURF_HLL) mhd_hll(un, &qn, ue[node], &qe[node], d, f);
+            else mhd_llf(un, &qn, ue[node], &qe[node], d, f);
+            for (int v = 0; v < 8; ++v) Sf[v] = Sf[v] - f[v] / m.w[0];
+          }
+        }
+        for (int v = 0; v < 8; ++v) R[v] = R[v] + (2.0 / m.h[d]) * (V[v] - Sf[v]);
+      }
+      for (int v = 0; v < 8; ++v) du[((int64_t)v * m.E + e) * NN + node] = R[v];
+    }
+  }
+  return bad ? ORC_ENONPHYS : ORC_OK;
+}
+
+/* dt = cfl 2 / ((N+1) max_e sum_d (2/h) max_nodes (|v_d| + c_f,d)). */
+int orc_mhd_max_dt(const orc_mhd_config *cfg, const double *u, double cfl, double *dt)
+{
+  mesh_t m;
+  int st = mhd_setup(cfg, &m);
+  if (st) return st;
+  const int NN = m.NN;
+  double lmax = 0.0;
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(max : lmax) reduction(| : bad)
+  for (int64_t e = 0; e < m.E; ++e) {
+    double lam = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      double mx = 0.0;
+      for (int node = 0; node < NN; ++node) {
+        double un[8];
+        mhd_prim_t q;
+        for (int v = 0; v < 8; ++v) un[v] = u[((int64_t)v * m.E + e) * NN + node];
+        bad |= mhd_to_prim(un, cfg->gamma, &q);
+        const double l = fabs(q.v[d]) + mhd_cf(&q, d);
+        if (l > mx) mx = l;
+      }
+      lam = lam + (2.0 / m.h[d]) * mx;
+    }
+    if (lam > lmax) lmax = lam;
+  }
+  *dt = cfl * 2.0 / ((m.N + 1) * lmax);
+  return bad ? ORC_ENONPHYS : ORC_OK;
+}
+
+int orc_mhd_step(const orc_mhd_config *cfg, double *u, int32_t nsteps, double cfl,
+                 double dt_fixed, double *t)
+{
+  const int64_t nodes = orc_mhd_num_nodes(cfg);
+  if (nodes < 0) return ORC_EINVAL;
+  const int64_t len = 8 * nodes;
+  double *k = calloc(len, sizeof(double)), *du = malloc(sizeof(double) * len);
+  double A[5], B[5];
+  orc_lsrk_coeffs(A, B, NULL);
+  int st = ORC_OK;
+  for (int step = 0; step < nsteps && st == ORC_OK; ++step) {
+    double dt = dt_fixed;
+    if (cfl > 0.0) st = orc_mhd_max_dt(cfg, u, cfl, &dt);
+    for (int s = 0; s < 5 && st == ORC_OK; ++s) {
+      st = orc_mhd_rhs(cfg, u, du);
+#pragma omp parallel for schedule(static)
+      for (int64_t i = 0; i < len; ++i) {
+        k[i] = A[s] * k[i] + dt * du[i];
+        u[i] = u[i] + B[s] * k[i];
+      }
+    }
+    if (t) *t = *t + dt;
+  }
+  free(k);
+  free(du);
+  return st;
+}
+
+/* Circularly polarised Alfven wave along e1 = (1,1,1)/sqrt 3 with wave vector k = pi (1,1,1)
+ * (period 2 in every direction): rho = 1, p = 0.1, B = B0 e1 + eps (cos phi e2 + sin phi e3),
+ * v = -(eps / sqrt rho)(cos phi e2 + sin phi e3), phi = k.x - |k| c_a t, c_a = B0/sqrt(rho),
+ * B0 = 1, eps = 0.1; e2 = (1,-1,0)/sqrt 2, e3 = e1 x e2.  An exact solution of ideal MHD. */
+int orc_mhd_alfven(double gamma, const double *x, double t, double *u)
+{
+  const double pi = 3.14159265358979323846;
+  const double rho = 1.0, p = 0.1, B0 = 1.0, eps = 0.1;
+  const double r3 = sqrt(3.0), r2 = sqrt(2.0), r6 = sqrt(6.0);
+  const double e1[3] = {1.0 / r3, 1.0 / r3, 1.0 / r3};
+  const double e2[3] = {1.0 / r2, -1.0 / r2, 0.0};
+  const double e3[3] = {1.0 / r6, 1.0 / r6, -2.0 / r6};   /* e1 x e2 */
+  const double ca = B0 / sqrt(rho);
+  const double phi = pi * (x[0] + x[1] + x[2]) - pi * r3 * ca * t;
+  const double c = cos(phi), s = sin(phi);
+  double v[3], B[3], v2 = 0.0, B2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    B[k] = B0 * e1[k] + eps * (c * e2[k] + s * e3[k]);
+    v[k] = -(eps / sqrt(rho)) * (c * e2[k] + s * e3[k]);
+    v2 = v2 + v[k] * v[k];
+    B2 = B2 + B[k] * B[k];
+  }
+  u[0] = rho;
+  for (int k = 0; k < 3; ++k) u[1 + k] = rho * v[k];
+  u[4] = p / (gamma - 1.0) + 0.5 * rho * v2 + 0.5 * B2;
+  for (int k = 0; k < 3; ++k) u[5 + k] = B[k];
+  return ORC_OK;
+}

@@ -116,6 +116,29 @@ int orc_curv_max_dt(const orc_curv_config *cfg, const double *u, double cfl, dou
 int orc_curv_step(const orc_curv_config *cfg, double *u, int32_t nsteps, double cfl,
                   double dt_fixed, double *t);
 
+/* Ideal MHD (the PID study's second system, Section 3.1): 8 variables
+ * u = (rho, rho v_1..3, E, B_1..3), mu_0 = 1, E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2, on the
+ * periodic Cartesian box [-1,1]^3 with cells^3 elements; weak-form DGSEM with the HLL (or
+ * LLF) interface flux, fast magnetosonic wave speeds; CK(5,4) with the CFL step. */
+typedef struct {
+  int32_t polydeg;
+  int32_t cells;
+  double  gamma;
+  int32_t surface;    /* ORC_SURF_HLL or ORC_SURF_LLF */
+} orc_mhd_config;
+
+int orc_mhd_flux(const double *u, int d, double gamma, double *f);          /* f^d(u), 8 */
+int orc_mhd_surface_flux(int kind, const double *uL, const double *uR, int d, double gamma,
+                         double *f);
+double orc_mhd_fast_speed(const double *u, int d, double gamma);
+int64_t orc_mhd_num_nodes(const orc_mhd_config *cfg);
+int orc_mhd_rhs(const orc_mhd_config *cfg, const double *u, double *du);   /* [8][E][n^3] */
+int orc_mhd_max_dt(const orc_mhd_config *cfg, const double *u, double cfl, double *dt);
+int orc_mhd_step(const orc_mhd_config *cfg, double *u, int32_t nsteps, double cfl,
+                 double dt_fixed, double *t);
+/* the circularly polarised Alfven wave (an exact solution) at one point */
+int orc_mhd_alfven(double gamma, const double *x, double t, double *u);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,7 +13,8 @@ from . import build as _build
 __all__ = ["Oracle", "OracleError", "NonPhysicalState", "lgl", "legendre_vinv", "ln_mean",
            "flux_phys", "flux_ec", "flux_central", "flux_llf", "flux_hll", "entropy",
            "entropy_vars", "lsrk_coeffs", "num_threads", "VOLUME", "SURFACE", "lib",
-           "CurvOracle", "curv_map", "curv_mms"]
+           "CurvOracle", "curv_map", "curv_mms", "MhdOracle", "mhd_flux", "mhd_surface_flux",
+           "mhd_fast_speed", "mhd_alfven"]
 
 VOLUME = {"ec": 0, "central": 1, "shockcap_hg": 2, "weak": 3, "none": 4}
 SURFACE = {"llf": 0, "hll": 1, "ec": 2, "none": 3}
@@ -39,6 +40,11 @@ class _CurvCfg(C.Structure):
     _fields_ = [("polydeg", C.c_int32), ("cells", C.c_int32), ("warp", C.c_double),
                 ("gamma", C.c_double), ("volume", C.c_int32), ("surface", C.c_int32),
                 ("source", C.c_int32)]
+
+
+class _MhdCfg(C.Structure):
+    _fields_ = [("polydeg", C.c_int32), ("cells", C.c_int32), ("gamma", C.c_double),
+                ("surface", C.c_int32)]
 
 
 _lib = None
@@ -83,6 +89,15 @@ def lib():
             ("orc_curv_max_dt", [C.POINTER(_CurvCfg), P, C.c_double, P], C.c_int),
             ("orc_curv_step", [C.POINTER(_CurvCfg), P, C.c_int32, C.c_double, C.c_double, P],
              C.c_int),
+            ("orc_mhd_flux", [P, C.c_int, C.c_double, P], C.c_int),
+            ("orc_mhd_surface_flux", [C.c_int, P, P, C.c_int, C.c_double, P], C.c_int),
+            ("orc_mhd_fast_speed", [P, C.c_int, C.c_double], C.c_double),
+            ("orc_mhd_num_nodes", [C.POINTER(_MhdCfg)], C.c_int64),
+            ("orc_mhd_rhs", [C.POINTER(_MhdCfg), P, P], C.c_int),
+            ("orc_mhd_max_dt", [C.POINTER(_MhdCfg), P, C.c_double, P], C.c_int),
+            ("orc_mhd_step", [C.POINTER(_MhdCfg), P, C.c_int32, C.c_double, C.c_double, P],
+             C.c_int),
+            ("orc_mhd_alfven", [C.c_double, P, C.c_double, P], C.c_int),
         ]:
             f = getattr(L, name)
             f.argtypes = args
@@ -339,3 +354,75 @@ class CurvOracle:
         _check(lib().orc_curv_step(C.byref(self.cfg), _p(u), int(nsteps), cfl, dt_fixed,
                                    C.byref(tt)), "step")
         return u.reshape(5, self.E, self.NN), tt.value
+
+
+# --------------------------------------------------------------------------- ideal MHD
+def mhd_flux(u, d, gamma=1.4):
+    f = np.zeros(8)
+    _check(lib().orc_mhd_flux(_p(_f64(u)), d, gamma, _p(f)), "mhd_flux")
+    return f
+
+
+def mhd_surface_flux(kind, uL, uR, d, gamma=1.4):
+    f = np.zeros(8)
+    _check(lib().orc_mhd_surface_flux(SURFACE[kind], _p(_f64(uL)), _p(_f64(uR)), d, gamma,
+                                      _p(f)), "mhd_surface_flux")
+    return f
+
+
+def mhd_fast_speed(u, d, gamma=1.4):
+    return lib().orc_mhd_fast_speed(_p(_f64(u)), d, gamma)
+
+
+def mhd_alfven(x, t, gamma=1.4):
+    u = np.zeros(8)
+    _check(lib().orc_mhd_alfven(gamma, _p(_f64(x)), float(t), _p(u)), "mhd_alfven")
+    return u
+
+
+class MhdOracle:
+    """Ideal MHD, weak form + HLL (or LLF), on [-1,1]^3 with cells^3 elements."""
+
+    def __init__(self, polydeg, cells, gamma=5.0 / 3.0, surface="hll"):
+        c = _MhdCfg()
+        c.polydeg, c.cells, c.gamma, c.surface = polydeg, cells, gamma, SURFACE[surface]
+        self.cfg = c
+        self.N, self.K, self.n = polydeg, cells, polydeg + 1
+        self.NN, self.E, self.gamma = self.n ** 3, cells ** 3, gamma
+        if lib().orc_mhd_num_nodes(C.byref(c)) < 0:
+            raise OracleError("invalid MHD configuration")
+        self._cart = Oracle(dim=3, polydeg=polydeg, cells=(cells,) * 3, xmin=(-1,) * 3,
+                            xmax=(1,) * 3, gamma=gamma)
+
+    def node_coords(self):
+        return self._cart.node_coords()
+
+    def _u(self, u):
+        u = _f64(u)
+        if u.size != 8 * self.E * self.NN:
+            raise ValueError("state has the wrong size")
+        return u
+
+    def alfven(self, t=0.0):
+        xyz = self.node_coords().reshape(3, -1)
+        u = np.stack([mhd_alfven(xyz[:, i], t, self.gamma) for i in range(xyz.shape[1])], axis=1)
+        return u.reshape(8, self.E, self.NN)
+
+    def rhs(self, u):
+        u = self._u(u)
+        du = np.zeros_like(u)
+        _check(lib().orc_mhd_rhs(C.byref(self.cfg), _p(u), _p(du)), "mhd_rhs")
+        return du.reshape(8, self.E, self.NN)
+
+    def max_dt(self, u, cfl):
+        dt = C.c_double(0.0)
+        _check(lib().orc_mhd_max_dt(C.byref(self.cfg), _p(self._u(u)), cfl, C.byref(dt)),
+               "mhd_max_dt")
+        return dt.value
+
+    def step(self, u, nsteps, cfl=0.5, dt_fixed=0.0, t=0.0):
+        u = self._u(u).copy()
+        tt = C.c_double(t)
+        _check(lib().orc_mhd_step(C.byref(self.cfg), _p(u), int(nsteps), cfl, dt_fixed,
+                                  C.byref(tt)), "mhd_step")
+        return u.reshape(8, self.E, self.NN), tt.value
