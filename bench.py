@@ -107,9 +107,9 @@ def main():
     ap.add_argument("--workload", default="tgv_32")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="rhs,mixed,batched,sedov,weak,curved,dwave",
+    ap.add_argument("--variants", default="rhs,mixed,batched,sedov,weak,curved,mhd,dwave",
                     help="comma list of extra variants: rhs, mixed, batched, sedov, weak, "
-                         "curved, dwave ('' for none)")
+                         "curved, mhd, dwave ('' for none)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -202,6 +202,12 @@ def main():
                 variants[f"{name}_mms_fp64"] = bench_curved(args, name)
             except Exception as e:
                 variants[f"{name}_mms_fp64"] = {"error": str(e)}
+    if "mhd" in want:
+        for name in ("alfven_4", "alfven_32"):
+            try:
+                variants[f"mhd_{name}_weak_hll_fp64"] = bench_mhd(args, name)
+            except Exception as e:
+                variants[f"mhd_{name}_weak_hll_fp64"] = {"error": str(e)}
     if "dwave" in want:
         try:
             variants["density_wave_2d_fp64"] = bench_density_wave(args)
@@ -310,6 +316,33 @@ def bench_curved(args, name):
         raise RuntimeError("non-physical state during the benchmark")
     return {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps,
             "ms_per_step": secs / steps * 1e3, "stage_us": round(avg_ms * 1e3, 2)}
+
+
+def bench_mhd(args, name):
+    """Ideal MHD, weak form + HLL, N = 3, on the Alfven wave: the paper's 4^3 mesh
+    (launch-bound) and 32^3 (the per-GPU size of tgv_32); full RK steps."""
+    import torch
+
+    from paper_2108_06476_amd import dgx, inputs
+    s = dgx.MhdSolver(**inputs.workload(name))
+    u = inputs.alfven(s.node_coords()).contiguous()
+    steps = max(10, args.steps // 2)
+    s.step(u, 2, cfl=0.5)
+    torch.cuda.synchronize()
+    s.profile_enable(True)
+    t0 = time.perf_counter()
+    s.step(u, steps, cfl=0.5)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    avg_ms, _, _ = s.profile_read()
+    s.profile_enable(False)
+    if s.check():
+        raise RuntimeError("non-physical state during the benchmark")
+    # stage traffic: 8 variables, 3 + 4 * 4 arrays per step over 5 stages (as for Euler)
+    gbs = 8 * 8 * 3.8 * s.num_nodes / (avg_ms * 1e-3) / 1e9
+    return {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps,
+            "ms_per_step": secs / steps * 1e3, "stage_us": round(avg_ms * 1e3, 2),
+            "stage_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def kernel_source_hash():

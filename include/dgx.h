@@ -186,6 +186,21 @@ dgx_status dgx_create_curved(const dgx_curv_config *cfg, void *hip_stream, dgx_h
  * jac [E][n^3] = J (device; either may be NULL).  DGX_EINVAL on a Cartesian handle. */
 dgx_status dgx_geometry(dgx_handle h, double *ja, double *jac);
 
+/* ---- ideal MHD (the PID study's second system, Section 3.1) --------------------------
+ * 8 variables u = (rho, rho v_1..3, E, B_1..3), mu_0 = 1, E = p/(gamma-1) + rho|v|^2/2 +
+ * |B|^2/2, on the periodic Cartesian box [-1,1]^3 with cells^3 elements: the weak-form DGSEM
+ * with the HLL (or LLF) interface flux and fast magnetosonic wave speeds.  The handle works
+ * with dgx_rhs, dgx_step (dt from sum_d (2/h) max (|v_d| + c_f,d)), dgx_max_dt,
+ * dgx_node_coords, dgx_check and the profiling calls; states are [8][E][n^3]. */
+typedef struct {
+  int32_t polydeg;        /* N; compiled for 1..7 */
+  int32_t cells;          /* elements per direction */
+  double  gamma;          /* > 1 */
+  int32_t surface;        /* DGX_SURF_HLL or DGX_SURF_LLF */
+} dgx_mhd_config;
+
+dgx_status dgx_create_mhd(const dgx_mhd_config *cfg, void *hip_stream, dgx_handle *out);
+
 /* Kernel timing for benchmarks: enables HIP-event timing of the dominant (stage) kernel on
  * the handle's stream.  One event pair brackets each run of back-to-back stage launches
  * (the five stages of an RK step; a single launch where indicator kernels sit between

@@ -158,6 +158,7 @@ struct dgx_solver {
   double* xyz = nullptr;    // node positions [3][E][NN]
   double* dmat = nullptr;   // LGL differentiation matrix [n][n]
   double* t0 = nullptr;     // start time of the current step
+  bool mhd = false;         // ideal MHD (dgx_create_mhd): 8 variables
   std::string err;
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -232,8 +233,9 @@ hipError_t launch_stage(dgx_handle h, const StageArgs& a, int epi, bool last) {
     hipError_t r = hipEventRecord(h->ev[h->ev_used], h->stream);
     if (r != hipSuccess) return r;
   }
-  hipError_t r = h->curved ? h->L->stage_curv(h->stream, a, h->g, h->cfg.volume, epi)
-                           : h->L->stage(h->stream, a, h->g, h->cfg.volume, epi, h->cfg.precision);
+  hipError_t r = h->mhd      ? h->L->stage_mhd(h->stream, a, h->g, epi)
+                 : h->curved ? h->L->stage_curv(h->stream, a, h->g, h->cfg.volume, epi)
+                             : h->L->stage(h->stream, a, h->g, h->cfg.volume, epi, h->cfg.precision);
   if (r != hipSuccess || !h->prof) return r;
   h->ev_count[pair] += 1;
   if (last) {   // close it
@@ -285,13 +287,14 @@ dgx_status enqueue_rhs(dgx_handle h, const double* u, double* du, const double* 
 
 // Per-element CFL partials of u into h->partial.
 hipError_t enqueue_maxspeed(dgx_handle h, const double* u) {
-  return h->curved ? h->L->maxspeed_curv(h->stream, u, h->partial, h->g)
-                   : h->L->maxspeed(h->stream, u, h->partial, h->g);
+  return h->mhd      ? h->L->maxspeed_mhd(h->stream, u, h->partial, h->g)
+         : h->curved ? h->L->maxspeed_curv(h->stream, u, h->partial, h->g)
+                     : h->L->maxspeed(h->stream, u, h->partial, h->g);
 }
 
 // The solver behind dgx_create (cv == nullptr) and dgx_create_curved.
 dgx_status create_impl(const dgx_config& c, const dgx_curv_config* cv, void* hip_stream,
-                       dgx_handle* out) {
+                       dgx_handle* out, bool mhd = false) {
   *out = nullptr;
   if (c.dim != 2 && c.dim != 3) return DGX_EINVAL;
   if (c.polydeg < 1) return DGX_EINVAL;
@@ -321,7 +324,8 @@ dgx_status create_impl(const dgx_config& c, const dgx_curv_config* cv, void* hip
   h->n = c.polydeg + 1;
   h->NN = c.dim == 3 ? h->n * h->n * h->n : h->n * h->n;
   h->NF = c.dim == 3 ? h->n * h->n : h->n;
-  h->NV = c.dim + 2;
+  h->NV = mhd ? 8 : c.dim + 2;
+  h->mhd = mhd;
   h->E = 1;
   for (int d = 0; d < 3; ++d) {
     const int K = d < c.dim ? c.cells[d] : 1;
@@ -446,6 +450,27 @@ dgx_status dgx_create_curved(const dgx_curv_config* cv, void* hip_stream, dgx_ha
   return create_impl(c, cv, hip_stream, out);
 }
 
+dgx_status dgx_create_mhd(const dgx_mhd_config* mc, void* hip_stream, dgx_handle* out) {
+  if (!mc || !out) return DGX_EINVAL;
+  *out = nullptr;
+  if (mc->polydeg < 1 || mc->cells < 1 || !(mc->gamma > 1.0)) return DGX_EINVAL;
+  if (mc->surface != DGX_SURF_HLL && mc->surface != DGX_SURF_LLF) return DGX_EINVAL;
+  dgx_config c{};
+  c.dim = 3;
+  c.polydeg = mc->polydeg;
+  for (int d = 0; d < 3; ++d) {
+    c.cells[d] = mc->cells;
+    c.xmin[d] = -1.0;
+    c.xmax[d] = 1.0;
+  }
+  c.gamma = mc->gamma;
+  c.volume = DGX_VOL_WEAK;   // the weak form's tables
+  c.surface = mc->surface;
+  c.fv_flux = DGX_SURF_LLF;
+  c.precision = DGX_FP64;
+  return create_impl(c, nullptr, hip_stream, out, true);
+}
+
 dgx_status dgx_geometry(dgx_handle h, double* ja, double* jac) {
   if (!h) return DGX_EINVAL;
   if (!h->curved) return fail(h, DGX_EINVAL, "dgx_geometry needs a curvilinear handle");
@@ -517,7 +542,7 @@ dgx_status dgx_rhs_alpha(dgx_handle h, const double* u, const double* alpha, dou
 dgx_status dgx_indicator(dgx_handle h, const double* u, double* alpha, double* alpha_raw,
                          double* energy) {
   if (!h) return DGX_EINVAL;
-  if (h->curved) return fail(h, DGX_EUNSUPPORTED, "no indicator on curvilinear handles");
+  if (h->curved || h->mhd) return fail(h, DGX_EUNSUPPORTED, "no indicator on this handle");
   CHKDEV(h, u, state_bytes(h), "u");
   CHKDEV(h, alpha, sizeof(double) * h->E, "alpha");
   if (alpha_raw) CHKDEV(h, alpha_raw, sizeof(double) * h->E, "alpha_raw");
@@ -593,7 +618,7 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
 
 dgx_status dgx_integrals(dgx_handle h, const double* u, const double* du, double* out7) {
   if (!h) return DGX_EINVAL;
-  if (h->curved) return fail(h, DGX_EUNSUPPORTED, "no integrals on curvilinear handles");
+  if (h->curved || h->mhd) return fail(h, DGX_EUNSUPPORTED, "no integrals on this handle");
   CHKDEV(h, u, state_bytes(h), "u");
   if (du) CHKDEV(h, du, state_bytes(h), "du");
   CHKDEV(h, out7, sizeof(double) * 7, "out7");

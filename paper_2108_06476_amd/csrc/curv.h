@@ -223,14 +223,21 @@ __device__ __forceinline__ void stage_tile_curv(typename CurvLdsOf<N, VOL>::type
     }
   }
   // next-step wave speed per reference direction: (|v . Ja^d| + c |Ja^d|) / J
-  stage_epilogue<3, N, EPI, 256>(s.xb, a, g, le, node, e, inb, active, ENN, own_ix, um, R,
-                                 [&](const Prim<double>& q, int d) {
-                                   double ad[3];
-                                   ja_of(s, d, li, ad);
-                                   const double va = q.v[0] * ad[0] + q.v[1] * ad[1] + q.v[2] * ad[2];
-                                   const double al = sqrt_pos(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]);
-                                   return (fabs(va) + q.c * al) * ij;
-                                 });
+  stage_epilogue<3, N, 5, EPI, 256>(
+      s.xb, a, g, le, node, e, inb, active, ENN, own_ix, um, R,
+      [&](const double (&un)[5], double (&ls)[3]) {
+        Prim<double> q;
+        const bool ok = cons_to_prim<3, false>(un, g.gamma, q);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          double ad[3];
+          ja_of(s, d, li, ad);
+          const double va = q.v[0] * ad[0] + q.v[1] * ad[1] + q.v[2] * ad[2];
+          const double al = sqrt_pos(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]);
+          ls[d] = (fabs(va) + q.c * al) * ij;
+        }
+        return ok;
+      });
 }
 
 template <int N, int VOL, int EPI>

@@ -529,17 +529,18 @@ __device__ __forceinline__ void weak_dir(const L& s, int base, int node, const d
 
 // Epilogue of a stage for one node: RHS: du = R; RK: k <- A k + dt R, u_out = u + B k and,
 // in the last stage, each element's partial of the next CFL step,
-// sum_d max_nodes speed(q, d) of the new state (speed: the direction's scaled wave speed).
+// sum_d max_nodes lam_d of the new state: speeds(u_new, lam) gives the directions' scaled
+// wave speeds and returns false for a non-physical state.
 // xb: the block's per-element LDS slots (elements of several waves reduce through them).
-template <int DIM, int N, int EPI, int BUDGET, typename SpeedFn>
+template <int DIM, int N, int NV, int EPI, int BUDGET, typename SpeedFn>
 __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArgs& a,
                                                const Geom& g, int le, int node, int e, bool inb,
                                                bool active, unsigned ENN, unsigned own_ix,
-                                               const double (&um)[DIM + 2],
-                                               const double (&R)[DIM + 2], SpeedFn speed) {
+                                               const double (&um)[NV], const double (&R)[NV],
+                                               SpeedFn speeds) {
   using S = Shape<DIM, N, BUDGET>;
   using SS = StageShape<DIM, N, double, BUDGET>;
-  constexpr int NV = S::NV, NN = S::NN;
+  constexpr int NN = S::NN;
   if constexpr (EPI == EPI_RHS) {
     if (active) {
 #pragma unroll
@@ -568,11 +569,11 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
     if (a.speed != nullptr) {
       if constexpr (WaveElem<DIM, N>::value) {
         if (active) {   // uniform per wave: the element is the wave
-          Prim<double> q;
-          if (!cons_to_prim<DIM, false>(un, g.gamma, q)) *g.flag = 1;
+          double ls[DIM];
+          if (!speeds(un, ls)) *g.flag = 1;
           double lam = 0.0;
 #pragma unroll
-          for (int d = 0; d < DIM; ++d) lam += wave_max_lane63(speed(q, d));
+          for (int d = 0; d < DIM; ++d) lam += wave_max_lane63(ls[d]);
           if (node == NN - 1) a.speed[e] = lam;
         }
       } else {
@@ -581,10 +582,10 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
         __syncthreads();
         if (inb) {
           if (active) {
-            Prim<double> q;
-            if (!cons_to_prim<DIM, false>(un, g.gamma, q)) *g.flag = 1;
+            double ls[DIM];
+            if (!speeds(un, ls)) *g.flag = 1;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) sp[d * NN + node] = speed(q, d);
+            for (int d = 0; d < DIM; ++d) sp[d * NN + node] = ls[d];
           } else {
 #pragma unroll
             for (int d = 0; d < DIM; ++d) sp[d * NN + node] = 0.0;
@@ -756,10 +757,15 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   }
 
   // ---- epilogue
-  stage_epilogue<DIM, N, EPI, BUDGET>(s.xb, a, g, le, node, e, inb, active, ENN, own_ix, um, R,
-                                      [&](const Prim<double>& q, int d) {
-                                        return sT[TAB_JAC + d] * (fabs(q.v[d]) + q.c);
-                                      });
+  stage_epilogue<DIM, N, NV, EPI, BUDGET>(
+      s.xb, a, g, le, node, e, inb, active, ENN, own_ix, um, R,
+      [&](const double (&un)[NV], double (&ls)[DIM]) {
+        Prim<double> q;
+        const bool ok = cons_to_prim<DIM, false>(un, g.gamma, q);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) ls[d] = sT[TAB_JAC + d] * (fabs(q.v[d]) + q.c);
+        return ok;
+      });
 }
 
 // The matrix-core variant asks for 4 waves per SIMD (its accumulators would otherwise push

@@ -1,0 +1,243 @@
+// mhd.h -- ideal MHD (the PID study's second system, Section 3.1) on the periodic Cartesian
+// box: the weak-form DGSEM with HLL or LLF interface fluxes in one fused RK stage kernel.
+// Variables u = (rho, rho v_1..3, E, B_1..3), mu_0 = 1, E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2:
+//   f^d(u) = (rho v_d, rho v_d v + p_t e_d - B_d B, v_d (E + p_t) - B_d (v.B), v_d B - B_d v),
+// p_t = p + |B|^2/2; wave speeds from the fast magnetosonic speed along d,
+//   c_f^2 = (a^2 + b^2 + sqrt((a^2 + b^2)^2 - 4 a^2 b_d^2))/2,
+// a^2 = gamma p/rho, b^2 = |B|^2/rho, b_d^2 = B_d^2/rho.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "kernels.h"
+
+namespace dgx {
+
+struct MhdPrim {
+  double rho, v[3], p, B[3], pt, c2, b2;
+};
+
+__device__ __forceinline__ bool mhd_prim(const double (&u)[8], double gamma, MhdPrim& q) {
+  q.rho = u[0];
+  const double inv = rcp_nr(u[0]);
+  double v2 = 0.0, B2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    q.v[k] = u[1 + k] * inv;
+    q.B[k] = u[5 + k];
+    v2 += q.v[k] * q.v[k];
+    B2 += q.B[k] * q.B[k];
+  }
+  q.p = (gamma - 1.0) * (u[4] - 0.5 * u[0] * v2 - 0.5 * B2);
+  q.pt = q.p + 0.5 * B2;
+  q.c2 = gamma * q.p * inv;
+  q.b2 = B2 * inv;
+  return (q.rho > 0.0) && (q.p > 0.0) && (q.p < 1.0e300) && (q.rho < 1.0e300);
+}
+
+template <int D>
+__device__ __forceinline__ void mhd_flux(const double (&u)[8], const MhdPrim& q, double (&f)[8]) {
+  const double vB = q.v[0] * q.B[0] + q.v[1] * q.B[1] + q.v[2] * q.B[2];
+  f[0] = u[1 + D];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f[1 + k] = u[1 + D] * q.v[k] + (k == D ? q.pt : 0.0) - q.B[D] * q.B[k];
+  f[4] = q.v[D] * (u[4] + q.pt) - q.B[D] * vB;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f[5 + k] = q.v[D] * q.B[k] - q.B[D] * q.v[k];
+}
+
+template <int D>
+__device__ __forceinline__ double mhd_cf(const MhdPrim& q) {
+  const double s = q.c2 + q.b2;
+  const double bd2 = q.B[D] * q.B[D] / q.rho;
+  const double disc = fmax(s * s - 4.0 * q.c2 * bd2, 0.0);
+  const double r = disc > 0.0 ? sqrt_pos(disc) : 0.0;
+  return sqrt_pos(0.5 * (s + r));
+}
+
+// Interface flux along D from the minus-side state L to the plus side R (HLL or LLF).
+template <int D>
+__device__ __forceinline__ void mhd_surface_flux(int surf, const double (&uL)[8], const MhdPrim& L,
+                                                 const double (&uR)[8], const MhdPrim& R,
+                                                 double (&f)[8]) {
+  double fL[8], fR[8];
+  mhd_flux<D>(uL, L, fL);
+  mhd_flux<D>(uR, R, fR);
+  const double cL = mhd_cf<D>(L), cR = mhd_cf<D>(R);
+  if (surf == SURF_LLF) {
+    const double lam = fmax(fabs(L.v[D]) + cL, fabs(R.v[D]) + cR);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
+    return;
+  }
+  const double sL = fmin(L.v[D] - cL, R.v[D] - cR);
+  const double sR = fmax(L.v[D] + cL, R.v[D] + cR);
+  if (sL >= 0.0) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) f[v] = fL[v];
+  } else if (sR <= 0.0) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) f[v] = fR[v];
+  } else {
+    const double inv = 1.0 / (sR - sL);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) f[v] = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) * inv;
+  }
+}
+
+template <int NE_NN, int XB>
+struct MhdLds {
+  double f[8][NE_NN];                  // one direction's physical fluxes of every node
+  alignas(16) unsigned char xb[XB];    // per element: wave speeds (elements of several waves)
+};
+
+template <int N>
+struct MhdLdsOf {
+  using SS = StageShape<3, N, double, 256>;
+  using type = MhdLds<SS::NENN, WaveElem<3, N>::value ? 16 : SS::XB>;
+};
+
+// Weak-form volume term and face term along D for one node: stage f^D of the element's
+// nodes, contract R += (2/h_D) sum_m Dhat_{i m} f^D(u_m) along the line, and for a face node
+// add the lifted interface flux (minus-side state first: both elements compute it alike).
+template <int N, int D, typename L>
+__device__ __forceinline__ void mhd_dir(L& s, const Geom& g, const StageArgs& a, const double* sT,
+                                        bool active, int e, const int (&ec)[3], int base,
+                                        int node, const double (&um)[8], const MhdPrim& qm,
+                                        double (&R)[8]) {
+  constexpr int n = N + 1, NN = Shape<3, N>::NN, st = Stride<D, n>::value;
+  const int id = (node / st) % n;
+  const int nb = base + node - id * st;
+  double f[8];
+  if (active) {
+    mhd_flux<D>(um, qm, f);
+#pragma unroll
+    for (int v = 0; v < 8; ++v) s.f[v][base + node] = f[v];
+  }
+  elem_sync<3, N>();
+  if (active) {
+#pragma unroll
+    for (int m = 0; m < n; ++m) {
+      const double c = sT[TAB_S + (D * TMAX + id) * TMAX + m];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) R[v] = fma(c, s.f[v][nb + m * st], R[v]);
+    }
+    if (a.surf != SURF_NONE && (id == 0 || id == N)) {
+      const bool plus = (id == N);
+      const int oth = plus ? node - N * st : node + N * st;
+      const int enb = elem_nb(g, e, ec, D, plus ? 1 : -1);
+      const unsigned ENN = (unsigned)g.E * NN;
+      double un[8], uL[8], uR[8], F[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) un[v] = a.uin[v * ENN + (unsigned)enb * NN + oth];
+      MhdPrim qn;
+      if (!mhd_prim(un, g.gamma, qn)) *g.flag = 1;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        uL[v] = plus ? um[v] : un[v];
+        uR[v] = plus ? un[v] : um[v];
+      }
+      mhd_surface_flux<D>(a.surf, uL, plus ? qm : qn, uR, plus ? qn : qm, F);
+      const double c = plus ? sT[TAB_LIFT + 2 * D + 1] : sT[TAB_LIFT + 2 * D];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) R[v] += c * F[v];
+    }
+  }
+  elem_sync<3, N>();   // the staged fluxes are read before the next direction overwrites them
+}
+
+template <int N, int EPI>
+__global__ __launch_bounds__((Shape<3, N>::THREADS)) void k_stage_mhd(StageArgs a, Geom g) {
+  using S = Shape<3, N>;
+  constexpr int NN = S::NN;
+  __shared__ typename MhdLdsOf<N>::type s;
+  __shared__ double sT[TAB_SIZE];
+  for (int i = threadIdx.x; i < TAB_SIZE; i += blockDim.x) sT[i] = g.tab[i];
+  const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
+  const int le = threadIdx.x / NN;
+  const int node = threadIdx.x - le * NN;
+  const int e = tile * S::NE + le;
+  const bool inb = le < S::NE;
+  const bool active = inb && (e < g.E);
+  const int base = le * NN;
+  const unsigned ENN = (unsigned)g.E * NN;
+  const unsigned own_ix = (unsigned)e * NN + node;
+  double um[8];
+  MhdPrim qm;
+  int ec[3] = {0, 0, 0};
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) um[v] = a.uin[v * ENN + own_ix];
+    if (!mhd_prim(um, g.gamma, qm)) *g.flag = 1;
+    elem_xyz(g, e, ec);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) um[v] = 0.0;
+    um[0] = 1.0;
+    um[4] = 1.0;
+    mhd_prim(um, g.gamma, qm);
+  }
+  double R[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) R[v] = 0.0;
+  __syncthreads();   // tables in LDS
+  mhd_dir<N, 0>(s, g, a, sT, active, e, ec, base, node, um, qm, R);
+  mhd_dir<N, 1>(s, g, a, sT, active, e, ec, base, node, um, qm, R);
+  mhd_dir<N, 2>(s, g, a, sT, active, e, ec, base, node, um, qm, R);
+  stage_epilogue<3, N, 8, EPI, 256>(
+      s.xb, a, g, le, node, e, inb, active, ENN, own_ix, um, R,
+      [&](const double (&un)[8], double (&ls)[3]) {
+        MhdPrim q;
+        const bool ok = mhd_prim(un, g.gamma, q);
+        ls[0] = sT[TAB_JAC + 0] * (fabs(q.v[0]) + mhd_cf<0>(q));
+        ls[1] = sT[TAB_JAC + 1] * (fabs(q.v[1]) + mhd_cf<1>(q));
+        ls[2] = sT[TAB_JAC + 2] * (fabs(q.v[2]) + mhd_cf<2>(q));
+        return ok;
+      });
+}
+
+// CFL partial per element: sum_d (2/h_d) max_nodes (|v_d| + c_f,d).
+template <int N>
+__global__ __launch_bounds__((Shape<3, N>::THREADS)) void k_maxspeed_mhd(
+    const double* __restrict__ u, double* __restrict__ partial, Geom g) {
+  using S = Shape<3, N>;
+  constexpr int NN = S::NN;
+  constexpr int P2 = NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
+  __shared__ double sm[3][S::NE * NN];
+  const int le = threadIdx.x / NN;
+  const int node = threadIdx.x - le * NN;
+  const int64_t e = (int64_t)blockIdx.x * S::NE + le;
+  const bool inb = le < S::NE;
+  const bool active = inb && (e < g.E);
+  const int base = le * NN;
+  const unsigned ENN = (unsigned)g.E * NN;
+  if (inb) {
+    if (active) {
+      double um[8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) um[v] = u[v * ENN + (unsigned)e * NN + node];
+      MhdPrim q;
+      if (!mhd_prim(um, g.gamma, q)) *g.flag = 1;
+      sm[0][base + node] = fabs(q.v[0]) + mhd_cf<0>(q);
+      sm[1][base + node] = fabs(q.v[1]) + mhd_cf<1>(q);
+      sm[2][base + node] = fabs(q.v[2]) + mhd_cf<2>(q);
+    } else {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sm[d][base + node] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int half = P2 / 2; half > 0; half >>= 1) {
+    if (inb && node < half && node + half < NN) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sm[d][base + node] = fmax(sm[d][base + node], sm[d][base + node + half]);
+    }
+    __syncthreads();
+  }
+  if (active && node == 0) {
+    double lam = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) lam += g.tab[TAB_JAC + d] * sm[d][base];
+    partial[e] = lam;
+  }
+}
+
+}  // namespace dgx

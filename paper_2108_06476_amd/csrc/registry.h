@@ -4,6 +4,7 @@
 
 #include "kernels.h"
 #include "curv.h"
+#include "mhd.h"
 
 namespace dgx {
 
@@ -26,6 +27,9 @@ struct Launchers {
   hipError_t (*maxspeed_curv)(hipStream_t, const double* u, double* partial, const Geom&) = nullptr;
   hipError_t (*geometry)(hipStream_t, const Geom&, const double* Dm, double warp, double* xyz,
                          double* ja, double* jac) = nullptr;
+  // ideal MHD, weak form (3D only)
+  hipError_t (*stage_mhd)(hipStream_t, const StageArgs&, const Geom&, int epi) = nullptr;
+  hipError_t (*maxspeed_mhd)(hipStream_t, const double* u, double* partial, const Geom&) = nullptr;
   const char* volume_name = "";
 };
 
@@ -147,6 +151,26 @@ struct Launch {
     return hipErrorInvalidValue;
   }
 
+  static hipError_t stage_mhd(hipStream_t st, const StageArgs& a, const Geom& g, int epi) {
+    if constexpr (DIM == 3) {
+      if (epi == EPI_RK)
+        hipLaunchKernelGGL((k_stage_mhd<N, EPI_RK>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st, a, g);
+      else
+        hipLaunchKernelGGL((k_stage_mhd<N, EPI_RHS>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st, a, g);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+
+  static hipError_t maxspeed_mhd(hipStream_t st, const double* u, double* partial, const Geom& g) {
+    if constexpr (DIM == 3) {
+      hipLaunchKernelGGL((k_maxspeed_mhd<N>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st, u,
+                         partial, g);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+
   static Launchers make() {
     Launchers L;
     L.threads = S::THREADS;
@@ -161,6 +185,8 @@ struct Launch {
       L.stage_curv = &stage_curv;
       L.maxspeed_curv = &maxspeed_curv;
       L.geometry = &geometry;
+      L.stage_mhd = &stage_mhd;
+      L.maxspeed_mhd = &maxspeed_mhd;
     }
     L.volume_name = "k_stage";
     return L;

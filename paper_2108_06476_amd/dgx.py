@@ -25,7 +25,8 @@ EXPORTS = ["dgx_create", "dgx_destroy", "dgx_set_stream", "dgx_num_nodes", "dgx_
            "dgx_step", "dgx_integrals", "dgx_check", "dgx_last_error", "dgx_profile_enable",
            "dgx_profile_read", "dgx_batch_create", "dgx_batch_destroy", "dgx_batch_num_nodes",
            "dgx_batch_step", "dgx_batch_rhs", "dgx_batch_tune", "dgx_batch_shape",
-           "dgx_batch_check", "dgx_batch_last_error", "dgx_create_curved", "dgx_geometry"]
+           "dgx_batch_check", "dgx_batch_last_error", "dgx_create_curved", "dgx_geometry",
+           "dgx_create_mhd"]
 
 
 class DgxError(RuntimeError):
@@ -53,6 +54,11 @@ class CurvConfig(C.Structure):
 
 
 SOURCE = {"none": 0, "mms": 1}
+
+
+class MhdConfig(C.Structure):
+    _fields_ = [("polydeg", C.c_int32), ("cells", C.c_int32), ("gamma", C.c_double),
+                ("surface", C.c_int32)]
 
 _lib = None
 
@@ -94,6 +100,7 @@ def lib():
             "dgx_batch_last_error": ([vp], C.c_char_p),
             "dgx_create_curved": ([C.POINTER(CurvConfig), vp, C.POINTER(vp)], C.c_int),
             "dgx_geometry": ([vp, vp, vp], C.c_int),
+            "dgx_create_mhd": ([C.POINTER(MhdConfig), vp, C.POINTER(vp)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -348,3 +355,27 @@ class CurvSolver(Solver):
         jac = torch.empty((self.E, self.NN), dtype=torch.float64, device="cuda")
         self._call("dgx_geometry", _ptr(ja, "ja"), _ptr(jac, "jac"))
         return ja, jac
+
+
+class MhdSolver(Solver):
+    """Ideal MHD (8 variables) on [-1,1]^3 with cells^3 elements: weak form + HLL or LLF
+    (dgx_create_mhd)."""
+
+    def __init__(self, polydeg, cells, gamma=5.0 / 3.0, surface="hll"):
+        c = MhdConfig()
+        c.polydeg, c.cells, c.gamma = polydeg, cells, gamma
+        c.surface = SURFACE[surface] if isinstance(surface, str) else int(surface)
+        self.mcfg = c
+        L = lib()
+        h = C.c_void_p()
+        st = L.dgx_create_mhd(C.byref(c), _stream(), C.byref(h))
+        if st != 0:
+            raise DgxError(st, "dgx_create_mhd failed (configuration not supported or invalid)")
+        self._h = h
+        self.dim, self.N = 3, polydeg
+        self.n = polydeg + 1
+        self.NN = self.n ** 3
+        self.nvar = 8
+        self.num_nodes = int(L.dgx_num_nodes(h))
+        self.E = int(L.dgx_num_elements(h))
+        self.shape = (8, self.E, self.NN)

@@ -55,6 +55,9 @@ def workload(name):
     if name in ("curved_4", "curved_32"):   # the PID study's warped box (Eq. (2)), MMS source
         return dict(polydeg=3, cells=4 if name == "curved_4" else 32, warp=0.15, gamma=GAMMA,
                     volume="ec", surface="llf", source="mms")
+    if name in ("alfven_4", "alfven_32"):   # ideal MHD, weak form + HLL, N = 3
+        return dict(polydeg=3, cells=4 if name == "alfven_4" else 32, gamma=5.0 / 3.0,
+                    surface="hll")
     if name == "tgv_64_mixed":      # mixed precision, N=3 on 64^3
         return dict(dim=3, polydeg=3, cells=(64, 64, 64), xmin=(-pi,) * 3, xmax=(pi,) * 3,
                     gamma=GAMMA, volume="ec", surface="llf", precision="mixed")
@@ -133,6 +136,25 @@ def mms(xyz, t=0.0):
     xp = _xp(xyz)
     rho = 2.0 + 0.1 * xp.sin(math.pi * (xyz[0] + xyz[1] + xyz[2]) - 2.0 * math.pi * t)
     return xp.stack([rho, rho, rho, rho, rho * rho])
+
+
+def alfven(xyz, t=0.0, gamma=5.0 / 3.0):
+    """Circularly polarised Alfven wave (ideal MHD, 8 variables) along e1 = (1,1,1)/sqrt 3
+    with wave vector pi (1,1,1): rho = 1, p = 0.1, B = e1 + 0.1 (cos phi e2 + sin phi e3),
+    v = -0.1 (cos phi e2 + sin phi e3), phi = pi (x+y+z) - pi sqrt(3) t, e2 = (1,-1,0)/sqrt 2,
+    e3 = e1 x e2 (numpy or torch coordinates)."""
+    xp = _xp(xyz)
+    r3, r2, r6 = math.sqrt(3.0), math.sqrt(2.0), math.sqrt(6.0)
+    e1 = (1 / r3, 1 / r3, 1 / r3)
+    e2 = (1 / r2, -1 / r2, 0.0)
+    e3 = (1 / r6, 1 / r6, -2 / r6)
+    phi = math.pi * (xyz[0] + xyz[1] + xyz[2]) - math.pi * r3 * t
+    c, s = xp.cos(phi), xp.sin(phi)
+    B = [e1[k] + 0.1 * (c * e2[k] + s * e3[k]) for k in range(3)]
+    v = [-0.1 * (c * e2[k] + s * e3[k]) for k in range(3)]
+    rho = xp.ones_like(c)
+    E = 0.1 / (gamma - 1.0) + 0.5 * sum(vk * vk for vk in v) + 0.5 * sum(Bk * Bk for Bk in B)
+    return xp.stack([rho] + v + [E] + B)
 
 
 def random_smooth(xyz, seed, amp=0.2, vamp=0.5, nmodes=4, periods=None):

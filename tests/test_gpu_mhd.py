@@ -1,0 +1,103 @@
+"""Ideal MHD on the GPU (dgx_create_mhd: weak form + HLL/LLF, 8 variables) against the MHD
+oracle, element by element.  Norm per field as in gpu_util: max|dR_v| / ((2/h) max(max|f_v|,
+lambda_max max|u_v|)) with the MHD fluxes and the fast magnetosonic speed; bar 1e-12."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2108_06476_amd import dgx, inputs
+
+from gpu_util import TOL_FP64, dev, host
+
+pytestmark = pytest.mark.gpu
+G = 5.0 / 3.0
+
+
+def _scale(u, h):
+    uu = u.reshape(8, -1)
+    F = np.zeros(8)
+    lam = 0.0
+    for i in range(0, uu.shape[1], max(1, uu.shape[1] // 2000)):
+        for d in range(3):
+            F = np.maximum(F, np.abs(oracle.mhd_flux(uu[:, i], d, G)))
+            lam = max(lam, abs(uu[1 + d, i] / uu[0, i]) + oracle.mhd_fast_speed(uu[:, i], d, G))
+    return (2.0 / h) * np.maximum(F, lam * np.abs(uu).max(axis=1))
+
+
+def _states(o, kind, seed):
+    if kind == "alfven":
+        return o.alfven(0.2)
+    rng = np.random.default_rng(seed)
+    xyz = o.node_coords()
+    g = inputs.random_smooth(xyz, seed, periods=[2.0] * 3)
+    u = np.zeros((8, o.E, o.NN))
+    u[0] = g[0]
+    u[1:4] = g[1:4]
+    Bv = 0.5 * inputs.random_smooth(xyz, seed + 1, periods=[2.0] * 3)[1:4] + rng.uniform(-0.5, 0.5, 3)[:, None, None]
+    rho = g[0]
+    p = 0.4 * (g[4] - 0.5 * (g[1:4] ** 2).sum(axis=0) / rho)
+    u[4] = p / (G - 1) + 0.5 * (g[1:4] ** 2).sum(axis=0) / rho + 0.5 * (Bv ** 2).sum(axis=0)
+    u[5:8] = Bv
+    if kind == "nodal":   # jumps at every interface
+        u = u * (1.0 + 0.05 * rng.uniform(-1, 1, u.shape))
+        u[4] = np.maximum(u[4], 0.5 * (u[1:4] ** 2).sum(axis=0) / u[0] + 0.5 * (u[5:8] ** 2).sum(axis=0) + 0.3)
+    return u
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("surf", ["hll", "llf"])
+@pytest.mark.parametrize("kind", ["alfven", "smooth", "nodal"])
+def test_mhd_rhs_parity(N, surf, kind):
+    K = 2 if N > 4 else 3
+    o = oracle.MhdOracle(N, K, surface=surf)
+    s = dgx.MhdSolver(N, K, surface=surf)
+    u = _states(o, kind, 60 + N)
+    ref = o.rhs(u)
+    got = host(s.rhs(dev(u)))
+    e = np.abs(got - ref).reshape(8, -1).max(axis=1) / _scale(u, 2.0 / K)
+    print(f"N={N} {surf} {kind}: err {e}", flush=True)
+    assert np.all(e <= TOL_FP64), e
+    assert s.check() == 0
+
+
+def test_mhd_thin_grid_and_free_stream():
+    o = oracle.MhdOracle(3, 1)
+    s = dgx.MhdSolver(3, 1)
+    u = _states(o, "nodal", 3)
+    e = np.abs(host(s.rhs(dev(u))) - o.rhs(u)).reshape(8, -1).max(axis=1) / _scale(u, 2.0)
+    assert np.all(e <= TOL_FP64), e
+    c = u[:, 0, :1]
+    uc = np.repeat(c, o.NN, axis=1)[:, None, :]
+    assert np.abs(host(s.rhs(dev(uc)))).max() <= 1e-13
+
+
+def test_mhd_max_dt_and_steps():
+    o = oracle.MhdOracle(3, 3)
+    s = dgx.MhdSolver(3, 3)
+    u0 = o.alfven(0.0)
+    dt = float(s.max_dt(dev(u0), 0.5).item())
+    np.testing.assert_allclose(dt, o.max_dt(u0, 0.5), rtol=1e-13)
+    ref, tref = o.step(u0, 10, cfl=0.5)
+    ud = dev(u0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.step(ud, 10, cfl=0.5, t=t)
+    d = np.abs(host(ud) - ref).max() / np.abs(ref).max()
+    print("mhd 10 steps: max|du|/max|u|", d, flush=True)
+    assert d <= 1e-12
+    np.testing.assert_allclose(float(t.item()), tref, rtol=1e-13)
+
+
+def test_mhd_gpu_input_generator_matches_oracle_wave():
+    o = oracle.MhdOracle(3, 2)
+    s = dgx.MhdSolver(3, 2)
+    ug = host(inputs.alfven(s.node_coords(), 0.3))
+    np.testing.assert_allclose(ug, o.alfven(0.3), rtol=1e-13, atol=1e-14)
+
+
+def test_mhd_rejections():
+    with pytest.raises(dgx.DgxError):
+        dgx.MhdSolver(3, 2, surface="ec")
+    s = dgx.MhdSolver(3, 2)
+    with pytest.raises(dgx.DgxError):
+        s.indicator(s.empty_state())
