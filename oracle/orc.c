@@ -1277,6 +1277,99 @@ static void mhd_llf(const double *uL, const mhd_prim_t *L, const double *uR, con
   for (int v = 0; v < 8; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
 }
 
+/* Entropy-conservative two-point flux of ideal MHD along d, with the Powell term
+ * phi(u) = (0, B, v.B, v) discretised as phi(u_i) {{B_d}}:  with beta = rho/(2p) the
+ * entropy condition  [[w]].f* + {{B_d}} [[w.phi]] = [[rho v_d + beta v_d |B|^2]]  and the
+ * discrete product rules give (averages {{a}} = (a_L + a_R)/2, log means of rho and beta)
+ *   f_rho = rho_ln {{v_d}}
+ *   f_rhov = f_rho {{v}} - {{B_d}} {{B}} + e_d ({{rho}}/(2 {{beta}}) + {{|B|^2}}/2)
+ *   f_B   = ({{beta v_d}}/{{beta}}) {{B}} - {{B_d}} {{v}}
+ *   f_E   = f_rho (1/(2(gamma-1) beta_ln) - {{|v|^2}}/2) + {{v}}.f_rhov + {{B}}.f_B
+ *           + {{B_d}} {{v.B}} - {{|B|^2}} {{v_d}}/2. */
+static void mhd_ec_flux(const mhd_prim_t *L, const mhd_prim_t *R, int d, double gamma, double *f)
+{
+  const double bL = L->rho / (2.0 * L->p), bR = R->rho / (2.0 * R->p);
+  const double rho_ln = orc_ln_mean(L->rho, R->rho), beta_ln = orc_ln_mean(bL, bR);
+  const double rho_a = 0.5 * (L->rho + R->rho), beta_a = 0.5 * (bL + bR);
+  double va[3], Ba[3], v2L = 0.0, v2R = 0.0, B2L = 0.0, B2R = 0.0, vBL = 0.0, vBR = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    va[k] = 0.5 * (L->v[k] + R->v[k]);
+    Ba[k] = 0.5 * (L->B[k] + R->B[k]);
+    v2L = v2L + L->v[k] * L->v[k];
+    v2R = v2R + R->v[k] * R->v[k];
+    B2L = B2L + L->B[k] * L->B[k];
+    B2R = B2R + R->B[k] * R->B[k];
+    vBL = vBL + L->v[k] * L->B[k];
+    vBR = vBR + R->v[k] * R->B[k];
+  }
+  const double v2a = 0.5 * (v2L + v2R), B2a = 0.5 * (B2L + B2R), vBa = 0.5 * (vBL + vBR);
+  const double bva = 0.5 * (bL * L->v[d] + bR * R->v[d]);
+  const double fr = rho_ln * va[d];
+  const double pt = rho_a / (2.0 * beta_a) + 0.5 * B2a;
+  f[0] = fr;
+  for (int k = 0; k < 3; ++k) {
+    f[1 + k] = fr * va[k] - Ba[d] * Ba[k] + (k == d ? pt : 0.0);
+    f[5 + k] = (bva / beta_a) * Ba[k] - Ba[d] * va[k];
+  }
+  double e = fr * (1.0 / (2.0 * (gamma - 1.0) * beta_ln) - 0.5 * v2a);
+  for (int k = 0; k < 3; ++k) e = e + va[k] * f[1 + k] + Ba[k] * f[5 + k];
+  f[4] = e + Ba[d] * vBa - 0.5 * B2a * va[d];
+}
+
+/* Powell's non-conservative term's coefficient phi(u) = (0, B, v.B, v). */
+static void mhd_phi(const mhd_prim_t *q, double *phi)
+{
+  phi[0] = 0.0;
+  double vB = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    phi[1 + k] = q->B[k];
+    phi[5 + k] = q->v[k];
+    vB = vB + q->v[k] * q->B[k];
+  }
+  phi[4] = vB;
+}
+
+static void mhd_face_flux(int kind, const double *uL, const mhd_prim_t *L, const double *uR,
+                          const mhd_prim_t *R, int d, double gamma, double *f)
+{
+  if (kind == ORC_SURF_HLL) mhd_hll(uL, L, uR, R, d, f);
+  else if (kind == ORC_SURF_LLF) mhd_llf(uL, L, uR, R, d, f);
+  else mhd_ec_flux(L, R, d, gamma, f);
+}
+
+/* S(u) = -rho s/(gamma-1), s = ln p - gamma ln rho; w = dS/du =
+ * ((gamma - s)/(gamma-1) - beta |v|^2, 2 beta v, -2 beta, 2 beta B), beta = rho/(2p). */
+double orc_mhd_entropy(const double *u, double gamma)
+{
+  mhd_prim_t q;
+  mhd_to_prim(u, gamma, &q);
+  return -q.rho * (log(q.p) - gamma * log(q.rho)) / (gamma - 1.0);
+}
+
+int orc_mhd_entropy_vars(const double *u, double gamma, double *w)
+{
+  mhd_prim_t q;
+  int bad = mhd_to_prim(u, gamma, &q);
+  const double s = log(q.p) - gamma * log(q.rho), beta = q.rho / (2.0 * q.p);
+  double v2 = 0.0;
+  for (int k = 0; k < 3; ++k) v2 = v2 + q.v[k] * q.v[k];
+  w[0] = (gamma - s) / (gamma - 1.0) - beta * v2;
+  for (int k = 0; k < 3; ++k) {
+    w[1 + k] = 2.0 * beta * q.v[k];
+    w[5 + k] = 2.0 * beta * q.B[k];
+  }
+  w[4] = -2.0 * beta;
+  return bad ? ORC_ENONPHYS : ORC_OK;
+}
+
+int orc_mhd_ec_flux(const double *uL, const double *uR, int d, double gamma, double *f)
+{
+  mhd_prim_t L, R;
+  int bad = mhd_to_prim(uL, gamma, &L) | mhd_to_prim(uR, gamma, &R);
+  mhd_ec_flux(&L, &R, d, gamma, f);
+  return bad ? ORC_ENONPHYS : ORC_OK;
+}
+
 int orc_mhd_flux(const double *u, int d, double gamma, double *f)
 {
   mhd_prim_t q;
@@ -1290,8 +1383,7 @@ int orc_mhd_surface_flux(int kind, const double *uL, const double *uR, int d, do
 {
   mhd_prim_t L, R;
   int bad = mhd_to_prim(uL, gamma, &L) | mhd_to_prim(uR, gamma, &R);
-  if (kind == ORC_SURF_HLL) mhd_hll(uL, &L, uR, &R, d, f);
-  else mhd_llf(uL, &L, uR, &R, d, f);
+  mhd_face_flux(kind, uL, &L, uR, &R, d, gamma, f);
   return bad ? ORC_ENONPHYS : ORC_OK;
 }
 
@@ -1305,7 +1397,10 @@ double orc_mhd_fast_speed(const double *u, int d, double gamma)
 static int mhd_setup(const orc_mhd_config *cfg, mesh_t *m)
 {
   if (!cfg || cfg->cells < 1) return ORC_EINVAL;
-  if (cfg->surface != ORC_SURF_HLL && cfg->surface != ORC_SURF_LLF) return ORC_EINVAL;
+  if (cfg->volume != ORC_VOL_WEAK && cfg->volume != ORC_VOL_EC) return ORC_EINVAL;
+  if (cfg->surface != ORC_SURF_HLL && cfg->surface != ORC_SURF_LLF &&
+      !(cfg->surface == ORC_SURF_EC && cfg->volume == ORC_VOL_EC))
+    return ORC_EINVAL;
   orc_config q;
   memset(&q, 0, sizeof(q));
   q.dim = 3;
@@ -1327,7 +1422,10 @@ int64_t orc_mhd_num_nodes(const orc_mhd_config *cfg)
 }
 
 /* Weak form: du = (2/h) sum_d [ sum_m Dhat_{i_d m} f^d(u_m)
- *                              - ([i_d == N] f*_{d+} - [i_d == 0] f*_{d-}) / w_0 ],
+ *                              - ([i_d == N] f*_{d+} - [i_d == 0] f*_{d-}) / w_0 ];
+ * flux differencing (volume ORC_VOL_EC): du = -(2/h) sum_d [ sum_{m != i_d} S_{i_d m}
+ *   (f*(u, u_m) + phi(u) {{B_d}}) + ([i_d == N] g_{d+} - [i_d == 0] g_{d-}) / w_0 ] with the
+ *   face terms g = F*(u_L, u_R) + phi(u) {{B_d}} (phi of the node's own state);
  * u laid out [8][E][NN] on the Cartesian box [-1,1]^3 (cells^3 elements). */
 int orc_mhd_rhs(const orc_mhd_config *cfg, const double *u, double *du)
 {
@@ -1351,13 +1449,21 @@ int orc_mhd_rhs(const orc_mhd_config *cfg, const double *u, double *du)
       double R[8] = {0, 0, 0, 0, 0, 0, 0, 0}, f[8];
       for (int d = 0; d < 3; ++d) {
         const int id = idx[d];
-        double V[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double V[8] = {0, 0, 0, 0, 0, 0, 0, 0}, phi[8];
+        mhd_phi(&qe[node], phi);
         for (int mm = 0; mm < n; ++mm) {
           int pidx[3] = {idx[0], idx[1], idx[2]};
           pidx[d] = mm;
           const int pn = node_of(&m, pidx);
-          mhd_flux(ue[pn], &qe[pn], d, f);
-          for (int v = 0; v < 8; ++v) V[v] = V[v] + m.Dhat[id * n + mm] * f[v];
+          if (cfg->volume == ORC_VOL_WEAK) {
+            mhd_flux(ue[pn], &qe[pn], d, f);
+            for (int v = 0; v < 8; ++v) V[v] = V[v] + m.Dhat[id * n + mm] * f[v];
+          } else if (mm != id) {
+            /* flux differencing: -(S_im (f*(u_i, u_m) + phi(u_i) {{B_d}})) */
+            mhd_ec_flux(&qe[node], &qe[pn], d, gamma, f);
+            const double Bm = 0.5 * (qe[node].B[d] + qe[pn].B[d]);
+            for (int v = 0; v < 8; ++v) V[v] = V[v] - m.S[id * n + mm] * (f[v] + phi[v] * Bm);
+          }
         }
         double Sf[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (id == N || id == 0) {
@@ -1369,15 +1475,15 @@ int orc_mhd_rhs(const orc_mhd_config *cfg, const double *u, double *du)
           mhd_prim_t qn;
           for (int v = 0; v < 8; ++v) un[v] = u[((int64_t)v * m.E + nb) * NN + pn];
           bad |= mhd_to_prim(un, gamma, &qn);
+          /* flux differencing adds the non-conservative face term phi(u_i) {{B_d}} */
+          const double Bf = cfg->volume == ORC_VOL_EC ? 0.5 * (qe[node].B[d] + qn.B[d]) : 0.0;
           if (id == N) {
-            if (cfg->surface == ORC_SURF_HLL) mhd_hll(ue[node], &qe[node], un, &qn, d, f);
-            else mhd_llf(ue[node], &qe[node], un, &qn, d, f);
-            for (int v = 0; v < 8; ++v) Sf[v] = Sf[v] + f[v] / m.w[N];
+            mhd_face_flux(cfg->surface, ue[node], &qe[node], un, &qn, d, gamma, f);
+            for (int v = 0; v < 8; ++v) Sf[v] = Sf[v] + (f[v] + phi[v] * Bf) / m.w[N];
           }
           if (id == 0) {
-            if (cfg->surface == ORC_SURF_HLL) mhd_hll(un, &qn, ue[node], &qe[node], d, f);
-            else mhd_llf(un, &qn, ue[node], &qe[node], d, f);
-            for (int v = 0; v < 8; ++v) Sf[v] = Sf[v] - f[v] / m.w[0];
+            mhd_face_flux(cfg->surface, un, &qn, ue[node], &qe[node], d, gamma, f);
+            for (int v = 0; v < 8; ++v) Sf[v] = Sf[v] - (f[v] + phi[v] * Bf) / m.w[0];
           }
         }
         for (int v = 0; v < 8; ++v) R[v] = R[v] + (2.0 / m.h[d]) * (V[v] - Sf[v]);

@@ -119,13 +119,22 @@ int orc_curv_step(const orc_curv_config *cfg, double *u, int32_t nsteps, double 
 /* Ideal MHD (the PID study's second system, Section 3.1): 8 variables
  * u = (rho, rho v_1..3, E, B_1..3), mu_0 = 1, E = p/(gamma-1) + rho|v|^2/2 + |B|^2/2, on the
  * periodic Cartesian box [-1,1]^3 with cells^3 elements; weak-form DGSEM with the HLL (or
- * LLF) interface flux, fast magnetosonic wave speeds; CK(5,4) with the CFL step. */
+ * LLF) interface flux, or flux differencing with an entropy-conservative two-point flux and
+ * Powell's non-conservative term (Section 3.1: the paper's MHD flux-differencing solver is
+ * entropy conservative and needs non-conservative terms); fast magnetosonic wave speeds;
+ * CK(5,4) with the CFL step. */
 typedef struct {
   int32_t polydeg;
   int32_t cells;
   double  gamma;
-  int32_t surface;    /* ORC_SURF_HLL or ORC_SURF_LLF */
+  int32_t surface;    /* ORC_SURF_HLL, ORC_SURF_LLF; ORC_SURF_EC with flux differencing */
+  int32_t volume;     /* ORC_VOL_WEAK, or ORC_VOL_EC: flux differencing with the
+                         entropy-conservative flux and Powell's non-conservative term */
 } orc_mhd_config;
+
+int orc_mhd_ec_flux(const double *uL, const double *uR, int d, double gamma, double *f);
+double orc_mhd_entropy(const double *u, double gamma);
+int orc_mhd_entropy_vars(const double *u, double gamma, double *w);
 
 int orc_mhd_flux(const double *u, int d, double gamma, double *f);          /* f^d(u), 8 */
 int orc_mhd_surface_flux(int kind, const double *uL, const double *uR, int d, double gamma,

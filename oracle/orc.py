@@ -14,7 +14,7 @@ __all__ = ["Oracle", "OracleError", "NonPhysicalState", "lgl", "legendre_vinv", 
            "flux_phys", "flux_ec", "flux_central", "flux_llf", "flux_hll", "entropy",
            "entropy_vars", "lsrk_coeffs", "num_threads", "VOLUME", "SURFACE", "lib",
            "CurvOracle", "curv_map", "curv_mms", "MhdOracle", "mhd_flux", "mhd_surface_flux",
-           "mhd_fast_speed", "mhd_alfven"]
+           "mhd_fast_speed", "mhd_alfven", "mhd_ec_flux", "mhd_entropy", "mhd_entropy_vars"]
 
 VOLUME = {"ec": 0, "central": 1, "shockcap_hg": 2, "weak": 3, "none": 4}
 SURFACE = {"llf": 0, "hll": 1, "ec": 2, "none": 3}
@@ -44,7 +44,7 @@ class _CurvCfg(C.Structure):
 
 class _MhdCfg(C.Structure):
     _fields_ = [("polydeg", C.c_int32), ("cells", C.c_int32), ("gamma", C.c_double),
-                ("surface", C.c_int32)]
+                ("surface", C.c_int32), ("volume", C.c_int32)]
 
 
 _lib = None
@@ -98,6 +98,9 @@ def lib():
             ("orc_mhd_step", [C.POINTER(_MhdCfg), P, C.c_int32, C.c_double, C.c_double, P],
              C.c_int),
             ("orc_mhd_alfven", [C.c_double, P, C.c_double, P], C.c_int),
+            ("orc_mhd_ec_flux", [P, P, C.c_int, C.c_double, P], C.c_int),
+            ("orc_mhd_entropy", [P, C.c_double], C.c_double),
+            ("orc_mhd_entropy_vars", [P, C.c_double, P], C.c_int),
         ]:
             f = getattr(L, name)
             f.argtypes = args
@@ -370,6 +373,22 @@ def mhd_surface_flux(kind, uL, uR, d, gamma=1.4):
     return f
 
 
+def mhd_ec_flux(uL, uR, d, gamma=1.4):
+    f = np.zeros(8)
+    _check(lib().orc_mhd_ec_flux(_p(_f64(uL)), _p(_f64(uR)), d, gamma, _p(f)), "mhd_ec_flux")
+    return f
+
+
+def mhd_entropy(u, gamma=1.4):
+    return lib().orc_mhd_entropy(_p(_f64(u)), gamma)
+
+
+def mhd_entropy_vars(u, gamma=1.4):
+    w = np.zeros(8)
+    _check(lib().orc_mhd_entropy_vars(_p(_f64(u)), gamma, _p(w)), "mhd_entropy_vars")
+    return w
+
+
 def mhd_fast_speed(u, d, gamma=1.4):
     return lib().orc_mhd_fast_speed(_p(_f64(u)), d, gamma)
 
@@ -381,11 +400,13 @@ def mhd_alfven(x, t, gamma=1.4):
 
 
 class MhdOracle:
-    """Ideal MHD, weak form + HLL (or LLF), on [-1,1]^3 with cells^3 elements."""
+    """Ideal MHD on [-1,1]^3 with cells^3 elements: weak form ("weak") or entropy-conservative
+    flux differencing with Powell's non-conservative term ("ec"); HLL, LLF or EC surface."""
 
-    def __init__(self, polydeg, cells, gamma=5.0 / 3.0, surface="hll"):
+    def __init__(self, polydeg, cells, gamma=5.0 / 3.0, surface="hll", volume="weak"):
         c = _MhdCfg()
         c.polydeg, c.cells, c.gamma, c.surface = polydeg, cells, gamma, SURFACE[surface]
+        c.volume = VOLUME[volume]
         self.cfg = c
         self.N, self.K, self.n = polydeg, cells, polydeg + 1
         self.NN, self.E, self.gamma = self.n ** 3, cells ** 3, gamma
