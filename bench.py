@@ -204,10 +204,11 @@ def main():
                 variants[f"{name}_mms_fp64"] = {"error": str(e)}
     if "mhd" in want:
         for name in ("alfven_4", "alfven_32"):
-            try:
-                variants[f"mhd_{name}_weak_hll_fp64"] = bench_mhd(args, name)
-            except Exception as e:
-                variants[f"mhd_{name}_weak_hll_fp64"] = {"error": str(e)}
+            for vol, tag in (("weak", "weak_hll"), ("ec", "ec_ec")):
+                try:
+                    variants[f"mhd_{name}_{tag}_fp64"] = bench_mhd(args, name, vol)
+                except Exception as e:
+                    variants[f"mhd_{name}_{tag}_fp64"] = {"error": str(e)}
     if "dwave" in want:
         try:
             variants["density_wave_2d_fp64"] = bench_density_wave(args)
@@ -318,13 +319,17 @@ def bench_curved(args, name):
             "ms_per_step": secs / steps * 1e3, "stage_us": round(avg_ms * 1e3, 2)}
 
 
-def bench_mhd(args, name):
-    """Ideal MHD, weak form + HLL, N = 3, on the Alfven wave: the paper's 4^3 mesh
-    (launch-bound) and 32^3 (the per-GPU size of tgv_32); full RK steps."""
+def bench_mhd(args, name, volume="weak"):
+    """Ideal MHD, N = 3, on the Alfven wave: weak form + HLL, or EC flux differencing with
+    Powell's term and EC surfaces; the paper's 4^3 mesh (launch-bound) and 32^3 (the
+    per-GPU size of tgv_32); full RK steps."""
     import torch
 
     from paper_2108_06476_amd import dgx, inputs
-    s = dgx.MhdSolver(**inputs.workload(name))
+    cfg = dict(inputs.workload(name))
+    if volume == "ec":
+        cfg.update(volume="ec", surface="ec")
+    s = dgx.MhdSolver(**cfg)
     u = inputs.alfven(s.node_coords()).contiguous()
     steps = max(10, args.steps // 2)
     s.step(u, 2, cfl=0.5)

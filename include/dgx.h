@@ -188,15 +188,20 @@ dgx_status dgx_geometry(dgx_handle h, double *ja, double *jac);
 
 /* ---- ideal MHD (the PID study's second system, Section 3.1) --------------------------
  * 8 variables u = (rho, rho v_1..3, E, B_1..3), mu_0 = 1, E = p/(gamma-1) + rho|v|^2/2 +
- * |B|^2/2, on the periodic Cartesian box [-1,1]^3 with cells^3 elements: the weak-form DGSEM
- * with the HLL (or LLF) interface flux and fast magnetosonic wave speeds.  The handle works
+ * |B|^2/2, on the periodic Cartesian box [-1,1]^3 with cells^3 elements, the two solvers of
+ * the paper's MHD comparison: volume = DGX_VOL_WEAK, the weak-form DGSEM with the HLL (or
+ * LLF) interface flux; volume = DGX_VOL_EC, flux differencing with an entropy-conservative
+ * two-point flux and Powell's non-conservative term phi(u) div B, phi = (0, B, v.B, v),
+ * discretised as phi(u_i) {{B_d}} in the volume and on the faces (surface EC, LLF or HLL;
+ * EC everywhere conserves the entropy exactly).  Fast magnetosonic wave speeds.  The handle works
  * with dgx_rhs, dgx_step (dt from sum_d (2/h) max (|v_d| + c_f,d)), dgx_max_dt,
  * dgx_node_coords, dgx_check and the profiling calls; states are [8][E][n^3]. */
 typedef struct {
   int32_t polydeg;        /* N; compiled for 1..7 */
   int32_t cells;          /* elements per direction */
   double  gamma;          /* > 1 */
-  int32_t surface;        /* DGX_SURF_HLL or DGX_SURF_LLF */
+  int32_t surface;        /* DGX_SURF_HLL or DGX_SURF_LLF; DGX_SURF_EC with DGX_VOL_EC */
+  int32_t volume;         /* DGX_VOL_WEAK or DGX_VOL_EC */
 } dgx_mhd_config;
 
 dgx_status dgx_create_mhd(const dgx_mhd_config *cfg, void *hip_stream, dgx_handle *out);

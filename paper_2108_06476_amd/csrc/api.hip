@@ -233,7 +233,7 @@ hipError_t launch_stage(dgx_handle h, const StageArgs& a, int epi, bool last) {
     hipError_t r = hipEventRecord(h->ev[h->ev_used], h->stream);
     if (r != hipSuccess) return r;
   }
-  hipError_t r = h->mhd      ? h->L->stage_mhd(h->stream, a, h->g, epi)
+  hipError_t r = h->mhd      ? h->L->stage_mhd(h->stream, a, h->g, h->cfg.volume, epi)
                  : h->curved ? h->L->stage_curv(h->stream, a, h->g, h->cfg.volume, epi)
                              : h->L->stage(h->stream, a, h->g, h->cfg.volume, epi, h->cfg.precision);
   if (r != hipSuccess || !h->prof) return r;
@@ -454,7 +454,10 @@ dgx_status dgx_create_mhd(const dgx_mhd_config* mc, void* hip_stream, dgx_handle
   if (!mc || !out) return DGX_EINVAL;
   *out = nullptr;
   if (mc->polydeg < 1 || mc->cells < 1 || !(mc->gamma > 1.0)) return DGX_EINVAL;
-  if (mc->surface != DGX_SURF_HLL && mc->surface != DGX_SURF_LLF) return DGX_EINVAL;
+  if (mc->volume != DGX_VOL_WEAK && mc->volume != DGX_VOL_EC) return DGX_EINVAL;
+  if (mc->surface != DGX_SURF_HLL && mc->surface != DGX_SURF_LLF &&
+      !(mc->surface == DGX_SURF_EC && mc->volume == DGX_VOL_EC))
+    return DGX_EINVAL;
   dgx_config c{};
   c.dim = 3;
   c.polydeg = mc->polydeg;
@@ -464,7 +467,7 @@ dgx_status dgx_create_mhd(const dgx_mhd_config* mc, void* hip_stream, dgx_handle
     c.xmax[d] = 1.0;
   }
   c.gamma = mc->gamma;
-  c.volume = DGX_VOL_WEAK;   // the weak form's tables
+  c.volume = mc->volume;   // the weak form's tables (Dhat) or flux differencing's (S)
   c.surface = mc->surface;
   c.fv_flux = DGX_SURF_LLF;
   c.precision = DGX_FP64;

@@ -194,6 +194,261 @@ __global__ __launch_bounds__((Shape<3, N>::THREADS)) void k_stage_mhd(StageArgs 
       });
 }
 
+// ---- entropy-conservative flux differencing with Powell's non-conservative term ----------
+// Node data of the pair flux: rho, v, beta = rho/(2p), B, and |v|^2, |B|^2, v.B.
+struct MhdNode {
+  double rho, v[3], beta, B[3], v2, B2, vB;
+};
+
+__device__ __forceinline__ MhdNode mhd_node(const MhdPrim& q) {
+  MhdNode a;
+  a.rho = q.rho;
+  a.beta = 0.5 * q.rho * rcp_nr(q.p);
+  a.v2 = a.B2 = a.vB = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a.v[k] = q.v[k];
+    a.B[k] = q.B[k];
+    a.v2 += q.v[k] * q.v[k];
+    a.B2 += q.B[k] * q.B[k];
+    a.vB += q.v[k] * q.B[k];
+  }
+  return a;
+}
+
+// The two-point flux along D that makes flux differencing with phi(u_i) {{B_D}} entropy
+// conservative: with beta = rho/(2p), the condition
+//   [[w]].f* + {{B_D}} [[w.phi]] = [[rho v_D + beta v_D |B|^2]],  phi = (0, B, v.B, v),
+// and the discrete product rules give
+//   f_rho = rho_ln {{v_D}},  f_rhov = f_rho {{v}} - {{B_D}} {{B}} + e_D ({{rho}}/(2{{beta}}) + {{|B|^2}}/2),
+//   f_B = ({{beta v_D}}/{{beta}}) {{B}} - {{B_D}} {{v}},
+//   f_E = f_rho (1/(2(gamma-1) beta_ln) - {{|v|^2}}/2) + {{v}}.f_rhov + {{B}}.f_B
+//         + {{B_D}} {{v.B}} - {{|B|^2}} {{v_D}}/2.
+template <int D>
+__device__ __forceinline__ void mhd_ec_flux(const MhdNode& L, const MhdNode& R, double inv_gm1,
+                                            double (&f)[8]) {
+  const double rho_ln = ln_mean(L.rho, R.rho);
+  const double ibeta = inv_ln_mean(L.beta, R.beta);
+  const double ba = 0.5 * (L.beta + R.beta);
+  const double iba = rcp_nr(ba);
+  double va[3], Ba[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    va[k] = 0.5 * (L.v[k] + R.v[k]);
+    Ba[k] = 0.5 * (L.B[k] + R.B[k]);
+  }
+  const double v2a = 0.5 * (L.v2 + R.v2), B2a = 0.5 * (L.B2 + R.B2), vBa = 0.5 * (L.vB + R.vB);
+  const double bva = 0.5 * (L.beta * L.v[D] + R.beta * R.v[D]);
+  const double fr = rho_ln * va[D];
+  const double pt = 0.25 * (L.rho + R.rho) * iba + 0.5 * B2a;
+  const double cb = bva * iba;
+  f[0] = fr;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    f[1 + k] = fr * va[k] - Ba[D] * Ba[k] + (k == D ? pt : 0.0);
+    f[5 + k] = cb * Ba[k] - Ba[D] * va[k];
+  }
+  double e = fr * (0.5 * inv_gm1 * ibeta - 0.5 * v2a);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) e += va[k] * f[1 + k] + Ba[k] * f[5 + k];
+  f[4] = e + Ba[D] * vBa - 0.5 * B2a * va[D];
+}
+
+template <int NE_NN, int XB>
+struct MhdEcLds {
+  double rho[NE_NN], v[3][NE_NN], beta[NE_NN], B[3][NE_NN], v2[NE_NN], B2[NE_NN], vB[NE_NN];
+  alignas(16) unsigned char xb[XB];   // per element: partner shares [8][NN] | wave speeds
+};
+
+template <int N>
+struct MhdEcLdsOf {
+  static constexpr int NN = Shape<3, N>::NN, NE = Shape<3, N>::NE;
+  static constexpr int SLOT = 8 * 8 * NN;   // eight float64 partner shares per node
+  using type = MhdEcLds<NE * NN, NE * SLOT>;
+};
+
+template <typename L>
+__device__ __forceinline__ MhdNode mhd_node_lds(const L& s, int i) {
+  MhdNode a;
+  a.rho = s.rho[i];
+  a.beta = s.beta[i];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a.v[k] = s.v[k][i];
+    a.B[k] = s.B[k][i];
+  }
+  a.v2 = s.v2[i];
+  a.B2 = s.B2[i];
+  a.vB = s.vB[i];
+  return a;
+}
+
+// Unique-pair rounds along D (as volume_dir) with the MHD EC flux; then Powell's term as the
+// node's phi times the contraction sum_{m != i} S_im {{B_D}}_im.
+template <int N, int D, typename L>
+__device__ __forceinline__ void mhd_ec_dir(const L& s, double* __restrict__ x, bool on, int base,
+                                           int node, const MhdNode& me, const double (&phi)[8],
+                                           const double* sS, double inv_gm1, double (&acc)[8]) {
+  constexpr int n = N + 1, st = Stride<D, n>::value, NN = Shape<3, N>::NN;
+  constexpr int FULL = (n - 1) / 2;
+  constexpr int ROUNDS = FULL + (n % 2 == 0 ? 1 : 0);
+  const int id = (node / st) % n;
+  const int nb = base + node - id * st;
+#pragma unroll
+  for (int r = 1; r <= ROUNDS; ++r) {
+    const bool half = (r > FULL);
+    int m = id + r;
+    if (m >= n) m -= n;
+    const int pn = nb + m * st;
+    if (on && (!half || id < n / 2)) {
+      const MhdNode q = mhd_node_lds(s, pn);
+      double f[8];
+      mhd_ec_flux<D>(me, q, inv_gm1, f);
+      const double cme = sS[(D * TMAX + id) * TMAX + m];
+      const double cpa = sS[(D * TMAX + m) * TMAX + id];
+#pragma unroll
+      for (int v = 0; v < 8; ++v) {
+        acc[v] += cme * f[v];
+        lds_add(&x[v * NN + pn - base], cpa * f[v]);
+      }
+    }
+    if constexpr (!WaveElem<3, N>::value) __syncthreads();
+  }
+  if (on) {
+    double c = 0.0;
+#pragma unroll
+    for (int m = 0; m < n; ++m)
+      if (m != id) c += sS[(D * TMAX + id) * TMAX + m] * (0.5 * (me.B[D] + s.B[D][nb + m * st]));
+#pragma unroll
+    for (int v = 0; v < 8; ++v) acc[v] += phi[v] * c;
+  }
+}
+
+// Face term along D for a boundary node: the interface flux (minus side first) plus the
+// node's phi times {{B_D}} across the face, lifted with -+(2/h)/w.
+template <int N, int D>
+__device__ __forceinline__ void mhd_ec_face(const Geom& g, const StageArgs& a, const double* sT,
+                                            int e, const int (&ec)[3], int node,
+                                            const double (&um)[8], const MhdPrim& qm,
+                                            const MhdNode& me, const double (&phi)[8],
+                                            double (&R)[8]) {
+  constexpr int n = N + 1, NN = Shape<3, N>::NN, st = Stride<D, n>::value;
+  const int id = (node / st) % n;
+  if (id != 0 && id != N) return;
+  const bool plus = (id == N);
+  const int oth = plus ? node - N * st : node + N * st;
+  const int enb = elem_nb(g, e, ec, D, plus ? 1 : -1);
+  const unsigned ENN = (unsigned)g.E * NN;
+  double un[8], uL[8], uR[8], F[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) un[v] = a.uin[v * ENN + (unsigned)enb * NN + oth];
+  MhdPrim qn;
+  if (!mhd_prim(un, g.gamma, qn)) *g.flag = 1;
+  if (a.surf == SURF_EC) {
+    const MhdNode nn = mhd_node(qn);
+    mhd_ec_flux<D>(plus ? me : nn, plus ? nn : me, 1.0 / (g.gamma - 1.0), F);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) {
+      uL[v] = plus ? um[v] : un[v];
+      uR[v] = plus ? un[v] : um[v];
+    }
+    mhd_surface_flux<D>(a.surf, uL, plus ? qm : qn, uR, plus ? qn : qm, F);
+  }
+  const double Bf = 0.5 * (qm.B[D] + qn.B[D]);
+  const double c = plus ? sT[TAB_LIFT + 2 * D + 1] : sT[TAB_LIFT + 2 * D];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) R[v] += c * (F[v] + phi[v] * Bf);
+}
+
+template <int N, int EPI>
+__global__ __launch_bounds__((Shape<3, N>::THREADS)) void k_stage_mhd_ec(StageArgs a, Geom g) {
+  using S = Shape<3, N>;
+  using LO = MhdEcLdsOf<N>;
+  constexpr int NN = S::NN;
+  __shared__ typename LO::type s;
+  __shared__ double sT[TAB_SIZE];
+  for (int i = threadIdx.x; i < TAB_SIZE; i += blockDim.x) sT[i] = g.tab[i];
+  const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
+  const int le = threadIdx.x / NN;
+  const int node = threadIdx.x - le * NN;
+  const int e = tile * S::NE + le;
+  const bool inb = le < S::NE;
+  const bool active = inb && (e < g.E);
+  const int base = le * NN;
+  const int li = base + node;
+  const unsigned ENN = (unsigned)g.E * NN;
+  const unsigned own_ix = (unsigned)e * NN + node;
+  double um[8], phi[8];
+  MhdPrim qm;
+  int ec[3] = {0, 0, 0};
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) um[v] = a.uin[v * ENN + own_ix];
+    if (!mhd_prim(um, g.gamma, qm)) *g.flag = 1;
+    elem_xyz(g, e, ec);
+  } else {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) um[v] = 0.0;
+    um[0] = 1.0;
+    um[4] = 1.0;
+    mhd_prim(um, g.gamma, qm);
+  }
+  const MhdNode me = mhd_node(qm);
+  phi[0] = 0.0;
+  phi[4] = me.vB;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    phi[1 + k] = me.B[k];
+    phi[5 + k] = me.v[k];
+  }
+  if (active) {
+    s.rho[li] = me.rho;
+    s.beta[li] = me.beta;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      s.v[k][li] = me.v[k];
+      s.B[k][li] = me.B[k];
+    }
+    s.v2[li] = me.v2;
+    s.B2[li] = me.B2;
+    s.vB[li] = me.vB;
+  }
+  double* x = reinterpret_cast<double*>(s.xb + (le < S::NE ? le : 0) * LO::SLOT);
+  if (inb) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) x[v * NN + node] = 0.0;
+  }
+  double R[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) R[v] = 0.0;
+  __syncthreads();
+  if (a.surf != SURF_NONE && active) {
+    mhd_ec_face<N, 0>(g, a, sT, e, ec, node, um, qm, me, phi, R);
+    mhd_ec_face<N, 1>(g, a, sT, e, ec, node, um, qm, me, phi, R);
+    mhd_ec_face<N, 2>(g, a, sT, e, ec, node, um, qm, me, phi, R);
+  }
+  const double inv_gm1 = 1.0 / (g.gamma - 1.0);
+  mhd_ec_dir<N, 0>(s, x, active, base, node, me, phi, sT + TAB_S, inv_gm1, R);
+  mhd_ec_dir<N, 1>(s, x, active, base, node, me, phi, sT + TAB_S, inv_gm1, R);
+  mhd_ec_dir<N, 2>(s, x, active, base, node, me, phi, sT + TAB_S, inv_gm1, R);
+  elem_sync<3, N>();   // every partner share has landed
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < 8; ++v) R[v] += x[v * NN + node];
+  }
+  stage_epilogue<3, N, 8, EPI, 256>(
+      s.xb, a, g, le, node, e, inb, active, ENN, own_ix, um, R,
+      [&](const double (&un)[8], double (&ls)[3]) {
+        MhdPrim q;
+        const bool ok = mhd_prim(un, g.gamma, q);
+        ls[0] = sT[TAB_JAC + 0] * (fabs(q.v[0]) + mhd_cf<0>(q));
+        ls[1] = sT[TAB_JAC + 1] * (fabs(q.v[1]) + mhd_cf<1>(q));
+        ls[2] = sT[TAB_JAC + 2] * (fabs(q.v[2]) + mhd_cf<2>(q));
+        return ok;
+      });
+}
+
 // CFL partial per element: sum_d (2/h_d) max_nodes (|v_d| + c_f,d).
 template <int N>
 __global__ __launch_bounds__((Shape<3, N>::THREADS)) void k_maxspeed_mhd(

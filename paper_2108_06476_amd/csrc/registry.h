@@ -28,7 +28,7 @@ struct Launchers {
   hipError_t (*geometry)(hipStream_t, const Geom&, const double* Dm, double warp, double* xyz,
                          double* ja, double* jac) = nullptr;
   // ideal MHD, weak form (3D only)
-  hipError_t (*stage_mhd)(hipStream_t, const StageArgs&, const Geom&, int epi) = nullptr;
+  hipError_t (*stage_mhd)(hipStream_t, const StageArgs&, const Geom&, int vol, int epi) = nullptr;
   hipError_t (*maxspeed_mhd)(hipStream_t, const double* u, double* partial, const Geom&) = nullptr;
   const char* volume_name = "";
 };
@@ -151,12 +151,16 @@ struct Launch {
     return hipErrorInvalidValue;
   }
 
-  static hipError_t stage_mhd(hipStream_t st, const StageArgs& a, const Geom& g, int epi) {
+  static hipError_t stage_mhd(hipStream_t st, const StageArgs& a, const Geom& g, int vol, int epi) {
     if constexpr (DIM == 3) {
-      if (epi == EPI_RK)
-        hipLaunchKernelGGL((k_stage_mhd<N, EPI_RK>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st, a, g);
-      else
-        hipLaunchKernelGGL((k_stage_mhd<N, EPI_RHS>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st, a, g);
+      const dim3 grid(blocks(g.E)), block(S::THREADS);
+      if (vol == VOL_EC) {
+        if (epi == EPI_RK) hipLaunchKernelGGL((k_stage_mhd_ec<N, EPI_RK>), grid, block, 0, st, a, g);
+        else hipLaunchKernelGGL((k_stage_mhd_ec<N, EPI_RHS>), grid, block, 0, st, a, g);
+      } else {
+        if (epi == EPI_RK) hipLaunchKernelGGL((k_stage_mhd<N, EPI_RK>), grid, block, 0, st, a, g);
+        else hipLaunchKernelGGL((k_stage_mhd<N, EPI_RHS>), grid, block, 0, st, a, g);
+      }
       return hipGetLastError();
     }
     return hipErrorInvalidValue;

@@ -58,7 +58,7 @@ SOURCE = {"none": 0, "mms": 1}
 
 class MhdConfig(C.Structure):
     _fields_ = [("polydeg", C.c_int32), ("cells", C.c_int32), ("gamma", C.c_double),
-                ("surface", C.c_int32)]
+                ("surface", C.c_int32), ("volume", C.c_int32)]
 
 _lib = None
 
@@ -358,13 +358,15 @@ class CurvSolver(Solver):
 
 
 class MhdSolver(Solver):
-    """Ideal MHD (8 variables) on [-1,1]^3 with cells^3 elements: weak form + HLL or LLF
-    (dgx_create_mhd)."""
+    """Ideal MHD (8 variables) on [-1,1]^3 with cells^3 elements (dgx_create_mhd): weak form
+    ("weak", HLL or LLF) or entropy-conservative flux differencing with Powell's term ("ec",
+    EC, LLF or HLL surface)."""
 
-    def __init__(self, polydeg, cells, gamma=5.0 / 3.0, surface="hll"):
+    def __init__(self, polydeg, cells, gamma=5.0 / 3.0, surface="hll", volume="weak"):
         c = MhdConfig()
         c.polydeg, c.cells, c.gamma = polydeg, cells, gamma
         c.surface = SURFACE[surface] if isinstance(surface, str) else int(surface)
+        c.volume = VOLUME[volume] if isinstance(volume, str) else int(volume)
         self.mcfg = c
         L = lib()
         h = C.c_void_p()

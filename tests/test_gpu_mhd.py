@@ -1,5 +1,6 @@
-"""Ideal MHD on the GPU (dgx_create_mhd: weak form + HLL/LLF, 8 variables) against the MHD
-oracle, element by element.  Norm per field as in gpu_util: max|dR_v| / ((2/h) max(max|f_v|,
+"""Ideal MHD on the GPU (dgx_create_mhd, 8 variables: weak form + HLL/LLF, and entropy-
+conservative flux differencing with Powell's non-conservative term + EC/LLF/HLL) against
+the MHD oracle, element by element.  Norm per field as in gpu_util: max|dR_v| / ((2/h) max(max|f_v|,
 lambda_max max|u_v|)) with the MHD fluxes and the fast magnetosonic speed; bar 1e-12."""
 import numpy as np
 import pytest
@@ -101,3 +102,43 @@ def test_mhd_rejections():
     s = dgx.MhdSolver(3, 2)
     with pytest.raises(dgx.DgxError):
         s.indicator(s.empty_state())
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 7])
+@pytest.mark.parametrize("surf", ["ec", "llf", "hll"])
+@pytest.mark.parametrize("kind", ["alfven", "smooth", "nodal"])
+def test_mhd_ec_rhs_parity(N, surf, kind):
+    K = 2 if N > 4 else 3
+    o = oracle.MhdOracle(N, K, surface=surf, volume="ec")
+    s = dgx.MhdSolver(N, K, surface=surf, volume="ec")
+    u = _states(o, kind, 80 + N)
+    ref = o.rhs(u)
+    got = host(s.rhs(dev(u)))
+    e = np.abs(got - ref).reshape(8, -1).max(axis=1) / _scale(u, 2.0 / K)
+    print(f"EC N={N} {surf} {kind}: err {e}", flush=True)
+    assert np.all(e <= TOL_FP64), e
+    assert s.check() == 0
+
+
+def test_mhd_ec_steps_and_thin_grid():
+    o = oracle.MhdOracle(3, 3, surface="llf", volume="ec")
+    s = dgx.MhdSolver(3, 3, surface="llf", volume="ec")
+    u0 = o.alfven(0.0)
+    ref, tref = o.step(u0, 10, cfl=0.5)
+    ud = dev(u0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.step(ud, 10, cfl=0.5, t=t)
+    d = np.abs(host(ud) - ref).max() / np.abs(ref).max()
+    print("mhd EC 10 steps: max|du|/max|u|", d, flush=True)
+    assert d <= 1e-12
+    np.testing.assert_allclose(float(t.item()), tref, rtol=1e-13)
+    o1 = oracle.MhdOracle(3, 1, surface="ec", volume="ec")
+    s1 = dgx.MhdSolver(3, 1, surface="ec", volume="ec")
+    u = _states(o1, "nodal", 9)
+    e = np.abs(host(s1.rhs(dev(u))) - o1.rhs(u)).reshape(8, -1).max(axis=1) / _scale(u, 2.0)
+    assert np.all(e <= TOL_FP64), e
+
+
+def test_mhd_ec_rejects_ec_surface_with_weak_volume():
+    with pytest.raises(dgx.DgxError):
+        dgx.MhdSolver(3, 2, surface="ec", volume="weak")
