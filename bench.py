@@ -99,6 +99,53 @@ def cpu_baseline(cfg, seconds):
                       f"{dt:.1f} s"}
 
 
+def cpu_baseline_1core(cfg, seconds):
+    """The oracle on one host core (the paper's PID study is serial), right-hand sides of the
+    same workload."""
+    import numpy as np
+
+    import oracle
+    from paper_2108_06476_amd import inputs
+    o = oracle.Oracle(**cfg)
+    u = inputs.tgv(o.node_coords())
+    prev = oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        n = 0
+        while True:
+            du = o.rhs(u)
+            n += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(prev)
+    assert np.isfinite(du).all()
+    return {"value": n * o.num_nodes / dt, "unit": "DOF-RHS/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} right-hand sides of the 32^3 N=3 TGV workload on one core, {dt:.1f} s"}
+
+
+def bench_rhs_graph(s, u, reps=20, replays=40):
+    """The right-hand side alone, reps launches captured once in a HIP graph and replayed."""
+    import torch
+    du = torch.empty_like(u)
+    s.rhs(u, du)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, capture_error_mode="relaxed"):
+        for _ in range(reps):
+            s.rhs(u, du)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        g.replay()
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    return {"value": reps * replays * s.num_nodes / secs, "unit": "DOF-RHS/s",
+            "rhs_per_graph": reps, "replays": replays}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,7 +201,9 @@ def main():
                                   "[-pi,pi]^3, EC volume + LLF surface, CK(5,4) RK at CFL 0.5",
                       "elements": s.E, "polydeg": 3, "dof_per_var": nodes,
                       "parallelism": "single GPU"},
-           "pid_s": 1.0 / value, "roofline": roofline}
+           "pid_s": 1.0 / value, "roofline": roofline,
+           # unique two-point volume fluxes per node and RHS: 3N/2 in 3D (4.5 at N = 3)
+           "unique_flux_evals_per_s": value * 1.5 * cfg["polydeg"]}
 
     variants = {}
     want = [v for v in args.variants.split(",") if v]
@@ -165,6 +214,10 @@ def main():
             variants["rhs_only_fp64"] = {"value": reps * nodes / t, "unit": "DOF-RHS/s"}
         except Exception as e:  # a failing variant must not hide the main line
             variants["rhs_only_fp64"] = {"error": str(e)}
+        try:
+            variants["rhs_only_fp64_hipgraph"] = bench_rhs_graph(s, u)
+        except Exception as e:
+            variants["rhs_only_fp64_hipgraph"] = {"error": str(e)}
     if "mixed" in want:
         try:
             for name in ("tgv_32", "tgv_64_mixed", "tgv_n7_32_mixed"):
@@ -218,6 +271,7 @@ def main():
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_seconds)
+        out["cpu_baseline_1core"] = cpu_baseline_1core(cfg, max(4.0, args.cpu_seconds / 2))
     print(json.dumps(out), flush=True)
 
 

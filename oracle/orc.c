@@ -762,6 +762,19 @@ int orc_integrals(const orc_config *cfg, const double *u, const double *du, doub
   return bad ? ORC_ENONPHYS : ORC_OK;
 }
 
+/* Number of OpenMP threads of the following calls; returns the previous number. */
+int orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+  const int prev = omp_get_max_threads();
+  if (n > 0) omp_set_num_threads(n);
+  return prev;
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

@@ -85,6 +85,7 @@ int orc_step(const orc_config *cfg, double *u, int32_t nsteps, double cfl, doubl
              double *t);
 int orc_integrals(const orc_config *cfg, const double *u, const double *du, double *out7);
 int orc_num_threads(void);
+int orc_set_num_threads(int n);   /* returns the previous number */
 
 /* Curvilinear mesh of the PID study (Section 3.1): the periodic box [-1,1]^3 with cells^3
  * elements, mapped by Eq. (2) with amplitude warp (0.15 in the paper; 0 gives the Cartesian

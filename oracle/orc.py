@@ -12,7 +12,7 @@ from . import build as _build
 
 __all__ = ["Oracle", "OracleError", "NonPhysicalState", "lgl", "legendre_vinv", "ln_mean",
            "flux_phys", "flux_ec", "flux_central", "flux_llf", "flux_hll", "entropy",
-           "entropy_vars", "lsrk_coeffs", "num_threads", "VOLUME", "SURFACE", "lib",
+           "entropy_vars", "lsrk_coeffs", "num_threads", "set_num_threads", "VOLUME", "SURFACE", "lib",
            "CurvOracle", "curv_map", "curv_mms", "MhdOracle", "mhd_flux", "mhd_surface_flux",
            "mhd_fast_speed", "mhd_alfven", "mhd_ec_flux", "mhd_entropy", "mhd_entropy_vars"]
 
@@ -80,6 +80,7 @@ def lib():
             ("orc_step", [CP, P, C.c_int32, C.c_double, C.c_double, P], C.c_int),
             ("orc_integrals", [CP, P, P, P], C.c_int),
             ("orc_num_threads", [], C.c_int),
+            ("orc_set_num_threads", [C.c_int], C.c_int),
             ("orc_curv_map", [C.c_double, P, P], C.c_int),
             ("orc_curv_mms", [C.c_double, P, C.c_double, P, P], C.c_int),
             ("orc_curv_num_nodes", [C.POINTER(_CurvCfg)], C.c_int64),
@@ -149,6 +150,11 @@ def lsrk_coeffs():
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the following oracle calls; returns the previous number."""
+    return lib().orc_set_num_threads(int(n))
 
 
 # --------------------------------------------------------------------------- pointwise
