@@ -360,17 +360,21 @@ def bench_curved(args, name):
     steps = max(10, args.steps // 2)
     s.step(u, 2, cfl=0.5, t=t)
     torch.cuda.synchronize()
-    s.profile_enable(True)
+    prof = not name.endswith("_4")   # the 4^3 mesh is timed on the graph-replay path
+    s.profile_enable(prof)
     t0 = time.perf_counter()
     s.step(u, steps, cfl=0.5, t=t)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    avg_ms, _, _ = s.profile_read()
+    avg_ms = s.profile_read()[0] if prof else float("nan")
     s.profile_enable(False)
     if s.check():
         raise RuntimeError("non-physical state during the benchmark")
-    return {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps,
-            "ms_per_step": secs / steps * 1e3, "stage_us": round(avg_ms * 1e3, 2)}
+    out = {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps,
+           "ms_per_step": secs / steps * 1e3}
+    if prof:
+        out["stage_us"] = round(avg_ms * 1e3, 2)
+    return out
 
 
 def bench_mhd(args, name, volume="weak"):
@@ -388,20 +392,23 @@ def bench_mhd(args, name, volume="weak"):
     steps = max(10, args.steps // 2)
     s.step(u, 2, cfl=0.5)
     torch.cuda.synchronize()
-    s.profile_enable(True)
+    prof = not name.endswith("_4")   # the 4^3 mesh is timed on the graph-replay path
+    s.profile_enable(prof)
     t0 = time.perf_counter()
     s.step(u, steps, cfl=0.5)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
-    avg_ms, _, _ = s.profile_read()
+    avg_ms = s.profile_read()[0] if prof else float("nan")
     s.profile_enable(False)
     if s.check():
         raise RuntimeError("non-physical state during the benchmark")
     # stage traffic: 8 variables, 3 + 4 * 4 arrays per step over 5 stages (as for Euler)
     gbs = 8 * 8 * 3.8 * s.num_nodes / (avg_ms * 1e-3) / 1e9
-    return {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps,
-            "ms_per_step": secs / steps * 1e3, "stage_us": round(avg_ms * 1e3, 2),
-            "stage_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    out = {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps,
+           "ms_per_step": secs / steps * 1e3}
+    if prof:
+        out.update(stage_us=round(avg_ms * 1e3, 2), stage_hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
+    return out
 
 
 def kernel_source_hash():

@@ -131,7 +131,10 @@ dgx_status dgx_max_dt(dgx_handle h, const double *u, double cfl, double *dt);
 /* Advance u in place by nsteps Carpenter-Kennedy 5-stage 4th-order 2N-storage
  * steps: per step dt from u at its start (cfl > 0) or dt_fixed (cfl <= 0), then
  * for s = 1..5: k <- A_s k + dt R(u), u <- u + B_s k.  t (device scalar, may be
- * NULL) is advanced by every dt.  The stage register lives in library scratch. */
+ * NULL) is advanced by every dt.  The stage register lives in library scratch.  Pairs of
+ * steps are replayed from a hipGraph that the handle captures once per (u, t, cfl,
+ * dt_fixed) and keeps; the result is bitwise that of launching every kernel (which the
+ * handle does while profiling is enabled). */
 dgx_status dgx_step(dgx_handle h, double *u, int32_t nsteps, double cfl, double dt_fixed,
                     double *t);
 

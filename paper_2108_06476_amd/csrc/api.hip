@@ -159,6 +159,13 @@ struct dgx_solver {
   double* dmat = nullptr;   // LGL differentiation matrix [n][n]
   double* t0 = nullptr;     // start time of the current step
   bool mhd = false;         // ideal MHD (dgx_create_mhd): 8 variables
+  // two RK steps captured in a hipGraph (replayed by dgx_step), valid for one key
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const double* g_u = nullptr;
+  const double* g_t = nullptr;
+  double g_cfl = 0.0, g_dtf = 0.0;
   std::string err;
   bool prof = false;
   std::vector<hipEvent_t> ev;
@@ -284,6 +291,80 @@ dgx_status enqueue_rhs(dgx_handle h, const double* u, double* du, const double* 
   return DGX_OK;
 }
 
+
+// One RK step on h->stream: dt (adaptive: from the partials in h->partial), then the five
+// stages; emit: the last stage writes the next step's partials.  cur: which of buf holds
+// the state (toggled by every stage).
+dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double cfl,
+                        double dt_fixed, double* t, bool emit) {
+  const bool adaptive = cfl > 0.0;
+  double* t0 = h->g.source ? h->t0 : nullptr;   // step start time for the stage times
+  if (adaptive) {
+    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, h->stream, h->partial, h->npart, cfl,
+                       (double)(h->N + 1), h->dt, t, t0);
+  } else {
+    hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, h->stream, dt_fixed, h->dt, t, t0);
+  }
+  HIPCHK(h, hipGetLastError());
+  for (int st = 0; st < 5; ++st) {
+    const double* uin = buf[cur];
+    const double* alpha = nullptr;
+    if (h->cfg.volume == DGX_VOL_SHOCKCAP_HG && !h->curved && !h->mhd) {
+      dgx_status r = enqueue_indicator(h, uin, h->alpha, h->alpha_raw, nullptr);
+      if (r != DGX_OK) return r;
+      alpha = h->alpha;
+    }
+    StageArgs a = stage_args(h, uin, alpha);
+    a.uout = buf[1 - cur];
+    a.A = CK_A[st];
+    a.B = CK_B[st];
+    a.speed = (adaptive && st == 4 && emit) ? h->partial : nullptr;
+    a.t0 = t0;
+    a.cs = CK_C[st];
+    // stages of one step run back to back unless indicator kernels sit between them
+    HIPCHK(h, launch_stage(h, a, EPI_RK, st == 4 || alpha != nullptr));
+    cur = 1 - cur;
+  }
+  return DGX_OK;
+}
+
+void drop_step_graph(dgx_handle h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  h->gexec = nullptr;
+  h->graph = nullptr;
+  h->g_u = nullptr;
+}
+
+// Two RK steps (both emitting the next partials) captured on a private stream; the graph
+// is reused while the state pointer, t and the step rule stay the same.
+dgx_status ensure_step_graph(dgx_handle h, double* u, double cfl, double dt_fixed, double* t) {
+  if (h->gexec && h->g_u == u && h->g_t == t && h->g_cfl == cfl && h->g_dtf == dt_fixed)
+    return DGX_OK;
+  drop_step_graph(h);
+  if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+  HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+  hipStream_t user = h->stream;
+  h->stream = h->cap;
+  double* buf[2] = {u, h->u2};
+  int cur = 0;
+  dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, true);
+  if (st == DGX_OK) st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, true);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(h->cap, &g);
+  h->stream = user;
+  if (st != DGX_OK || e != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return st != DGX_OK ? st : fail(h, DGX_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  }
+  h->graph = g;
+  HIPCHK(h, hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+  h->g_u = u;
+  h->g_t = t;
+  h->g_cfl = cfl;
+  h->g_dtf = dt_fixed;
+  return DGX_OK;
+}
 
 // Per-element CFL partials of u into h->partial.
 hipError_t enqueue_maxspeed(dgx_handle h, const double* u) {
@@ -498,6 +579,8 @@ dgx_status dgx_destroy(dgx_handle h) {
                   (void*)h->jac, (void*)h->xyz, (void*)h->dmat, (void*)h->t0})
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  drop_step_graph(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   delete h;
   return DGX_OK;
 }
@@ -575,41 +658,22 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
   if (t) CHKDEV(h, t, sizeof(double), "t");
   if (h->g.source && !t) return fail(h, DGX_EINVAL, "the source term needs the device time t");
   if (nsteps == 0) return DGX_OK;
-  double* t0 = h->g.source ? h->t0 : nullptr;   // step start time for the stage times
   const bool adaptive = cfl > 0.0;
   // the state alternates between u and the library's u2, stage by stage: a stage reads the
   // neighbours' face states of its input while other blocks write their output
   double* buf[2] = {u, h->u2};
   int cur = 0;
   if (adaptive) HIPCHK(h, enqueue_maxspeed(h, u));
-  for (int s = 0; s < nsteps; ++s) {
-    if (adaptive) {
-      // partials: from the wave-speed pass (first step) or from the last stage of the step before
-      hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, h->stream, h->partial, h->npart, cfl,
-                         (double)(h->N + 1), h->dt, t, t0);
-    } else {
-      hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, h->stream, dt_fixed, h->dt, t, t0);
-    }
-    HIPCHK(h, hipGetLastError());
-    for (int st = 0; st < 5; ++st) {
-      const double* uin = buf[cur];
-      const double* alpha = nullptr;
-      if (h->cfg.volume == DGX_VOL_SHOCKCAP_HG) {
-        dgx_status r = enqueue_indicator(h, uin, h->alpha, h->alpha_raw, nullptr);
-        if (r != DGX_OK) return r;
-        alpha = h->alpha;
-      }
-      StageArgs a = stage_args(h, uin, alpha);
-      a.uout = buf[1 - cur];
-      a.A = CK_A[st];
-      a.B = CK_B[st];
-      a.speed = (adaptive && st == 4 && s + 1 < nsteps) ? h->partial : nullptr;
-      a.t0 = t0;
-      a.cs = CK_C[st];
-      // stages of one step run back to back unless indicator kernels sit between them
-      HIPCHK(h, launch_stage(h, a, EPI_RK, st == 4 || alpha != nullptr));
-      cur = 1 - cur;
-    }
+  int s = 0;
+  if (nsteps >= 2 && !h->prof) {
+    // pairs of steps from the captured graph (ten stages: the state is back in u)
+    dgx_status st = ensure_step_graph(h, u, cfl, dt_fixed, t);
+    if (st != DGX_OK) return st;
+    for (; s + 2 <= nsteps; s += 2) HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
+  }
+  for (; s < nsteps; ++s) {
+    dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, s + 1 < nsteps);
+    if (st != DGX_OK) return st;
   }
   if (cur != 0) {
     const int64_t n = (int64_t)h->NV * h->E * h->NN;
