@@ -89,12 +89,6 @@ __device__ __forceinline__ int elem_nb(const Geom& g, int e, const int (&c)[3], 
   return e + (x - cd) * sd;
 }
 
-template <int n, int D>
-__device__ __forceinline__ int face_index(int node) {
-  constexpr int st = Stride<D, n>::value;
-  return (node % st) + (node / (st * n)) * st;
-}
-
 // Orders LDS accesses of one wavefront: the wait retires the wave's outstanding LDS
 // operations and the memory clobber keeps the compiler from moving any memory access
 // across this point (the wave-barrier intrinsic alone does not order memory).

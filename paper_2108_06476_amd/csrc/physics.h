@@ -215,71 +215,6 @@ __device__ __forceinline__ void hll_flux(const double (&uL)[DIM + 2], const Prim
 
 enum { SURF_LLF = 0, SURF_HLL = 1, SURF_EC = 2, SURF_NONE = 3 };
 
-template <int DIM, int D, int SURF>
-__device__ __forceinline__ void surface_flux(const double (&uL)[DIM + 2], const Prim<double>& L,
-                                             const double (&uR)[DIM + 2], const Prim<double>& R,
-                                             double gamma, double (&f)[DIM + 2]) {
-  if constexpr (SURF == SURF_LLF) llf_flux<DIM, D>(uL, L, uR, R, gamma, f);
-  else if constexpr (SURF == SURF_HLL) hll_flux<DIM, D>(uL, L, uR, R, gamma, f);
-  else ec_flux<DIM, D, double>(L, R, 1.0 / (gamma - 1.0), f);
-}
-
-// ---- runtime normal direction d (one code path for every face of an element) -------
-
-template <int DIM>
-__device__ __forceinline__ double pick(const double (&a)[3], int d) {
-  return DIM == 3 ? (d == 0 ? a[0] : (d == 1 ? a[1] : a[2])) : (d == 0 ? a[0] : a[1]);
-}
-
-template <int DIM>
-__device__ __forceinline__ void phys_flux_rt(const double (&u)[DIM + 2], const Prim<double>& q,
-                                             int d, double vn, double (&f)[DIM + 2]) {
-  const double mn = DIM == 3 ? (d == 0 ? u[1] : (d == 1 ? u[2] : u[3])) : (d == 0 ? u[1] : u[2]);
-  f[0] = mn;
-#pragma unroll
-  for (int k = 0; k < DIM; ++k) f[1 + k] = mn * q.v[k] + (k == d ? q.p : 0.0);
-  f[DIM + 1] = vn * (u[DIM + 1] + q.p);
-}
-
-template <int DIM>
-__device__ __forceinline__ void surface_flux_rt(int surf, int d, const double (&uL)[DIM + 2],
-                                                const Prim<double>& L, const double (&uR)[DIM + 2],
-                                                const Prim<double>& R, double gamma,
-                                                double (&f)[DIM + 2]) {
-  const double vL = pick<DIM>(L.v, d), vR = pick<DIM>(R.v, d);
-  if (surf == SURF_EC) {
-    const double rho_ln = ln_mean(L.rho, R.rho);
-    const double ibeta = inv_ln_mean(L.beta, R.beta);
-    double vLvR = L.v[0] * R.v[0];
-#pragma unroll
-    for (int k = 1; k < DIM; ++k) vLvR += L.v[k] * R.v[k];
-    const double frho = rho_ln * (0.5 * (vL + vR));
-    const double pavg = 0.5 * (L.p + R.p);
-    f[0] = frho;
-#pragma unroll
-    for (int k = 0; k < DIM; ++k) f[1 + k] = frho * (0.5 * (L.v[k] + R.v[k])) + (k == d ? pavg : 0.0);
-    f[DIM + 1] = frho * (ibeta * (1.0 / (gamma - 1.0)) + 0.5 * vLvR) + 0.5 * (L.p * vR + R.p * vL);
-    return;
-  }
-  double fL[DIM + 2], fR[DIM + 2];
-  phys_flux_rt<DIM>(uL, L, d, vL, fL);
-  phys_flux_rt<DIM>(uR, R, d, vR, fR);
-  if (surf == SURF_LLF) {
-    const double lam = fmax(fabs(vL) + L.c, fabs(vR) + R.c);
-#pragma unroll
-    for (int v = 0; v < DIM + 2; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
-    return;
-  }
-  const double sL = fmin(vL - L.c, vR - R.c);
-  const double sR = fmax(vL + L.c, vR + R.c);
-  const double inv = rcp_nr(sR - sL);
-#pragma unroll
-  for (int v = 0; v < DIM + 2; ++v) {
-    const double mid = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) * inv;
-    f[v] = sL >= 0.0 ? fL[v] : (sR <= 0.0 ? fR[v] : mid);
-  }
-}
-
 }  // namespace dgx
 
 namespace dgx {
