@@ -367,10 +367,12 @@ __device__ __forceinline__ void face_load(const double* __restrict__ u, const Ge
   if (id != 0 && id != N) return;
   const bool plus = (id == N);
   const int oth = plus ? node - N * st : node + N * st;
-  const int enb = elem_nb(g, e, ec, D, plus ? 1 : -1);
+  // both neighbours' indices first (uniform when e is), then one per-lane choice
+  const int enbp = elem_nb(g, e, ec, D, 1), enbm = elem_nb(g, e, ec, D, -1);
+  const unsigned off = (unsigned)(plus ? enbp : enbm) * NN + (unsigned)oth;
   const unsigned ENN = (unsigned)g.E * NN;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) un[v] = u[v * ENN + (unsigned)enb * NN + oth];
+  for (int v = 0; v < NV; ++v) un[v] = (u + (size_t)v * ENN)[off];
 }
 
 template <int DIM, int N, int D>
@@ -538,7 +540,7 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
   if constexpr (EPI == EPI_RHS) {
     if (active) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) a.du[v * ENN + own_ix] = R[v];
+      for (int v = 0; v < NV; ++v) (a.du + (size_t)(own_ix - node) + (size_t)v * ENN)[(unsigned)node] = R[v];
     }
   } else {
     double un[NV];
@@ -550,14 +552,14 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
         for (int v = 0; v < NV; ++v) kv[v] = dt * R[v];
       } else {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) kv[v] = a.A * a.k[v * ENN + own_ix] + dt * R[v];
+        for (int v = 0; v < NV; ++v) kv[v] = a.A * (a.k + (size_t)(own_ix - node) + (size_t)v * ENN)[(unsigned)node] + dt * R[v];
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        const unsigned ix = v * ENN + own_ix;
-        a.k[ix] = kv[v];
+        const size_t pb = (size_t)(own_ix - node) + (size_t)v * ENN;   // uniform plane base
+        a.k[pb + (unsigned)node] = kv[v];
         un[v] = um[v] + a.B * kv[v];
-        a.uout[ix] = un[v];
+        a.uout[pb + (unsigned)node] = un[v];
       }
     }
     if (a.speed != nullptr) {
@@ -615,8 +617,12 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   using SS = StageShape<DIM, N, RT, BUDGET>;
   constexpr int NV = S::NV, NN = S::NN;
   constexpr bool CONS = (VOL == VOL_CENTRAL || VOL == VOL_SHOCKCAP);
-  const int le = threadIdx.x / NN;
-  const int node = threadIdx.x - le * NN;
+  // A wavefront never spans two elements whose node count is a multiple of 64: the element
+  // index is then wave-uniform, and its arithmetic (coordinates, neighbours, plane offsets)
+  // and the active-element branch move to the scalar unit.
+  const int le = NN % 64 == 0 ? __builtin_amdgcn_readfirstlane(threadIdx.x / NN)
+                              : (int)(threadIdx.x / NN);
+  const int node = (int)(threadIdx.x % (unsigned)NN);
   const int e = tile * S::NE + le;
   const bool inb = le < S::NE;
   const bool active = inb && (e < g.E);
@@ -629,7 +635,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   Prim<double> qd;
   if (active) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) um[v] = a.uin[v * ENN + own_ix];
+    for (int v = 0; v < NV; ++v) um[v] = (a.uin + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
     if (a.surf != SURF_NONE) {
       int ec[3];
       elem_xyz(g, e, ec);
