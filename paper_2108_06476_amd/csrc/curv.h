@@ -139,8 +139,8 @@ __device__ __forceinline__ void stage_tile_curv(typename CurvLdsOf<N, VOL>::type
   using S = Shape<3, N>;
   using SS = StageShape<3, N, double, 256>;
   constexpr int NV = 5, NN = S::NN;
-  const int le = threadIdx.x / NN;
-  const int node = threadIdx.x - le * NN;
+  const int le = elem_slot<NN>();
+  const int node = (int)(threadIdx.x % (unsigned)NN);
   const int e = tile * S::NE + le;
   const bool inb = le < S::NE;
   const bool active = inb && (e < g.E);
@@ -154,7 +154,7 @@ __device__ __forceinline__ void stage_tile_curv(typename CurvLdsOf<N, VOL>::type
   double ij = 1.0;   // 1/J of this node
   if (active) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) um[v] = a.uin[v * ENN + own_ix];
+    for (int v = 0; v < NV; ++v) um[v] = (a.uin + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
     if (a.surf != SURF_NONE) {
       int ec[3];
       elem_xyz(g, e, ec);
@@ -321,8 +321,8 @@ __global__ __launch_bounds__((Shape<3, N>::THREADS)) void k_maxspeed_curv(
   constexpr int NN = S::NN;
   constexpr int P2 = NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
   __shared__ double sm[3][S::NE * NN];
-  const int le = threadIdx.x / NN;
-  const int node = threadIdx.x - le * NN;
+  const int le = elem_slot<NN>();
+  const int node = (int)(threadIdx.x % (unsigned)NN);
   const int64_t e = (int64_t)blockIdx.x * S::NE + le;
   const bool inb = le < S::NE;
   const bool active = inb && (e < g.E);

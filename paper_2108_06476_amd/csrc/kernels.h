@@ -129,6 +129,15 @@ __device__ __forceinline__ double wave_max_lane63(double x) {
   return x;
 }
 
+// The element slot of this thread in its block.  A wavefront never spans two elements whose
+// node count is a multiple of 64: the slot is then wave-uniform, and the element's index
+// arithmetic (coordinates, neighbours, plane offsets) and its active branch run on the
+// scalar unit.
+template <int NN>
+__device__ __forceinline__ int elem_slot() {
+  return NN % 64 == 0 ? __builtin_amdgcn_readfirstlane(threadIdx.x / NN) : (int)(threadIdx.x / NN);
+}
+
 template <int DIM, int N>
 __device__ __forceinline__ void elem_sync() {
   if constexpr (WaveElem<DIM, N>::value) wave_sync();
@@ -211,7 +220,7 @@ __device__ __forceinline__ void volume_dir(const L& s, double* __restrict__ x /*
                                            bool on, int base,
                                            int node, const Prim<RT>& me,
                                            const double (&ume)[DIM + 2], const double* sS,
-                                           RT inv_gm1, RT (&acc)[DIM + 2]) {
+                                           RT inv_gm1, RT pref, RT (&acc)[DIM + 2]) {
   constexpr int n = N + 1, st = Stride<D, n>::value;
   constexpr int NN = Shape<DIM, N>::NN;
   constexpr int FULL = (n - 1) / 2;
@@ -249,6 +258,8 @@ __device__ __forceinline__ void volume_dir(const L& s, double* __restrict__ x /*
         central_flux<DIM, D>(ume, med, uq, qd, fd);
 #pragma unroll
         for (int v = 0; v < DIM + 2; ++v) f[v] = (RT)fd[v];
+      } else if constexpr (sizeof(RT) == 4) {
+        ec_flux_pp<DIM, D>(me, q, inv_gm1, pref, f);
       } else {
         ec_flux<DIM, D, RT>(me, q, inv_gm1, f);
       }
@@ -274,7 +285,7 @@ __device__ __forceinline__ void volume_dir(const L& s, double* __restrict__ x /*
 template <int DIM, int N, typename RT, typename L>
 __device__ __forceinline__ void volume_xy_half(const L& s, double* __restrict__ x, bool on,
                                                int base, int node, const Prim<RT>& me,
-                                               const double* sS, RT inv_gm1,
+                                               const double* sS, RT inv_gm1, RT pref,
                                                RT (&acc)[DIM + 2]) {
   constexpr int n = N + 1, h = n / 2;
   constexpr int NN = Shape<DIM, N>::NN;
@@ -297,7 +308,8 @@ __device__ __forceinline__ void volume_xy_half(const L& s, double* __restrict__ 
     q.v[0] = dy ? q1 : q0;
     q.v[1] = dy ? q0 : q1;
     RT f[DIM + 2];
-    ec_flux<DIM, 0, RT>(a, q, inv_gm1, f);
+    if constexpr (sizeof(RT) == 4) ec_flux_pp<DIM, 0>(a, q, inv_gm1, pref, f);
+    else ec_flux<DIM, 0, RT>(a, q, inv_gm1, f);
     const RT f1 = f[1], f2 = f[2];
     f[1] = dy ? f2 : f1;
     f[2] = dy ? f1 : f2;
@@ -379,7 +391,7 @@ template <int DIM, int N, int D>
 __device__ __forceinline__ void surface_dir(const Geom& g, int surf, int node,
                                             const double (&um)[DIM + 2], const Prim<double>& qm,
                                             const double (&un)[DIM + 2], const double* sL,
-                                            double (&R)[DIM + 2]) {
+                                            double pref, double (&R)[DIM + 2]) {
   using S = Shape<DIM, N>;
   constexpr int n = S::n, NV = S::NV, st = Stride<D, n>::value;
   const int id = (node / st) % n;
@@ -423,6 +435,9 @@ __device__ __forceinline__ void surface_dir(const Geom& g, int surf, int node,
     qR.c = plus ? qn.c : qm.c;
     hll_flux<DIM, D>(uL, qL, uR, qR, g.gamma, F);
   }
+  // pref: the constant pressure left out of a float32 volume sum (0 in float64), removed
+  // from the lifted normal momentum flux with it
+  F[1 + D] -= pref;
   const double c = plus ? sL[2 * D + 1] : sL[2 * D];
 #pragma unroll
   for (int v = 0; v < NV; ++v) R[v] += c * F[v];
@@ -617,11 +632,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   using SS = StageShape<DIM, N, RT, BUDGET>;
   constexpr int NV = S::NV, NN = S::NN;
   constexpr bool CONS = (VOL == VOL_CENTRAL || VOL == VOL_SHOCKCAP);
-  // A wavefront never spans two elements whose node count is a multiple of 64: the element
-  // index is then wave-uniform, and its arithmetic (coordinates, neighbours, plane offsets)
-  // and the active-element branch move to the scalar unit.
-  const int le = NN % 64 == 0 ? __builtin_amdgcn_readfirstlane(threadIdx.x / NN)
-                              : (int)(threadIdx.x / NN);
+  const int le = elem_slot<NN>();
   const int node = (int)(threadIdx.x % (unsigned)NN);
   const int e = tile * S::NE + le;
   const bool inb = le < S::NE;
@@ -630,12 +641,24 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   const unsigned ENN = (unsigned)g.E * NN;
   const unsigned own_ix = (unsigned)e * NN + node;
 
+  static_assert(sizeof(RT) == 8 || VOL == VOL_EC, "float32 volume fluxes: EC flux differencing only");
   double um[NV];
   double unb[DIM][NV];   // neighbours' face-node states, loaded up front
   Prim<double> qd;
+  // float32 volume sums take the pressure relative to one reference per element (node 0's),
+  // so they carry no large constant part; the constant's volume sum, p_ref times the row sum
+  // of -(2/h_d) S (minus the lift factor at a face node, zero inside), cancels exactly
+  // against p_ref in the lifted surface flux, which is removed there in float64 instead.
+  double pref = 0.0;
   if (active) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) um[v] = (a.uin + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
+    if constexpr (sizeof(RT) == 4 && !WaveElem<DIM, N>::value) {
+      double u0[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u0[v] = a.uin[(size_t)e * NN + (size_t)v * ENN];
+      pref = pressure<DIM>(u0, g.gamma);
+    }
     if (a.surf != SURF_NONE) {
       int ec[3];
       elem_xyz(g, e, ec);
@@ -644,6 +667,10 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
       if constexpr (DIM == 3) face_load<DIM, N, 2>(a.uin, g, e, ec, node, unb[2]);
     }
     if (!cons_to_prim<DIM>(um, g.gamma, qd)) *g.flag = 1;
+    if constexpr (sizeof(RT) == 4 && WaveElem<DIM, N>::value) {   // the wave is the element
+      pref = __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(qd.p)),
+                              __builtin_amdgcn_readfirstlane(__double2loint(qd.p)));
+    }
     const int li = base + node;
     if constexpr (VOL == VOL_WEAK || VOL == VOL_WEAK_MFMA) {   // physical fluxes of this node
       double f[NV];
@@ -663,7 +690,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
       s.rho[li] = (RT)qd.rho;
 #pragma unroll
       for (int k = 0; k < DIM; ++k) s.v[k][li] = (RT)qd.v[k];
-      s.p[li] = (RT)qd.p;
+      s.p[li] = (RT)(qd.p - pref);
       s.beta[li] = (RT)qd.beta;
       if constexpr (CONS) {
 #pragma unroll
@@ -689,9 +716,9 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
 
   // ---- surface: each boundary node's face flux, lifted onto the node
   if (a.surf != SURF_NONE && active) {
-    surface_dir<DIM, N, 0>(g, a.surf, node, um, qd, unb[0], sT + TAB_LIFT, R);
-    surface_dir<DIM, N, 1>(g, a.surf, node, um, qd, unb[1], sT + TAB_LIFT, R);
-    if constexpr (DIM == 3) surface_dir<DIM, N, 2>(g, a.surf, node, um, qd, unb[2], sT + TAB_LIFT, R);
+    surface_dir<DIM, N, 0>(g, a.surf, node, um, qd, unb[0], sT + TAB_LIFT, pref, R);
+    surface_dir<DIM, N, 1>(g, a.surf, node, um, qd, unb[1], sT + TAB_LIFT, pref, R);
+    if constexpr (DIM == 3) surface_dir<DIM, N, 2>(g, a.surf, node, um, qd, unb[2], sT + TAB_LIFT, pref, R);
   }
 
   // ---- volume
@@ -710,7 +737,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     me.rho = (RT)qd.rho;
 #pragma unroll
     for (int k = 0; k < 3; ++k) me.v[k] = (RT)qd.v[k];
-    me.p = (RT)qd.p;
+    me.p = (RT)(qd.p - pref);
     me.beta = (RT)qd.beta;
     const RT inv_gm1 = (RT)(1.0 / (g.gamma - 1.0));
     // float64 without blending: the surface terms seed the volume accumulator (fewer live
@@ -721,12 +748,12 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     for (int v = 0; v < NV; ++v) acc[v] = SEED ? (RT)R[v] : RT(0);
     // even n with the EC flux: the x and y half rounds run as one packed round
     constexpr bool PACK = (N % 2 == 1) && (VOL == VOL_EC || VOL == VOL_SHOCKCAP);
-    volume_dir<DIM, N, 0, VOL, RT, !PACK>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
-    volume_dir<DIM, N, 1, VOL, RT, !PACK>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
+    volume_dir<DIM, N, 0, VOL, RT, !PACK>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, (RT)pref, acc);
+    volume_dir<DIM, N, 1, VOL, RT, !PACK>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, (RT)pref, acc);
     if constexpr (PACK)
-      volume_xy_half<DIM, N, RT>(s, x, active, base, node, me, sT + TAB_S, inv_gm1, acc);
+      volume_xy_half<DIM, N, RT>(s, x, active, base, node, me, sT + TAB_S, inv_gm1, (RT)pref, acc);
     if constexpr (DIM == 3)
-      volume_dir<DIM, N, 2, VOL, RT, true>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, acc);
+      volume_dir<DIM, N, 2, VOL, RT, true>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, (RT)pref, acc);
     elem_sync<DIM, N>();   // every partner share has landed
     if (active) {
 #pragma unroll

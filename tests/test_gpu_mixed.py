@@ -4,9 +4,17 @@ means, interface fluxes, lift, RK accumulation and reductions) against the float
 The mixed path is an approximation of the float64 method, so the check is a stated error
 bound, not 1e-12 parity.  Bound on the right-hand side, per field in the flux-scale norm of
 gpu_util: each node sums 3N volume terms of size up to the flux scale, each carrying a
-relative float32 rounding of a few units of 2^-24 (6e-8) from the flux algebra, plus the
-float32 accumulation; 3N * 4 * 6e-8 = 7e-6 at N = 7, 3e-6 at N = 3.  The tests assert 2e-5
-and print the measured errors.
+relative float32 rounding of a few units of 2^-24 from the flux algebra and the float32
+accumulation; with 8 units per term the bound is 3N * 8 * 2^-24 (4.3e-6 at N = 3, 1.0e-5 at
+N = 7).
+
+The float32 volume sums take the pressure relative to a per-element reference (the constant
+part cancels exactly against the lifted surface flux in float64): the float32 momentum terms
+are then of size rho v v_d + (p - p_ref), about 1.3 at Mach 0.1 against a flux scale of
+rho v v_d + p of about 72, and the momentum error stays below 1e-6 (with absolute pressures in
+float32 it was 3e-6 at N = 3 and 1.4e-5 at N = 7).  The log means' float32 series branch
+extends to z^2 < 1e-2 (truncation 1.1e-9), which keeps the float32 logarithm away from
+b/a near 1.
 """
 import math
 
@@ -21,7 +29,13 @@ from gpu_util import dev, err_v, host, rel_to_max
 
 pytestmark = pytest.mark.gpu
 
-MIXED_RHS_BOUND = 2e-5
+
+
+def mixed_bound(polydeg):
+    return 3 * polydeg * 8 * 2.0 ** -24
+
+
+MOMENTUM_BOUND_MACH01 = 1e-6
 
 
 @pytest.mark.parametrize("name,cells", [("tgv_64_mixed", (64, 64, 64)), ("tgv_n7_32_mixed", (16, 16, 16)),
@@ -36,7 +50,8 @@ def test_mixed_rhs_error(name, cells):
     h = (cfg["xmax"][0] - cfg["xmin"][0]) / cells[0]
     e = err_v(got, ref, u, 3, h)
     print(f"mixed {name} {cells}: err_v {e}  rel_to_max {rel_to_max(got, ref)}", flush=True)
-    assert np.all(e <= MIXED_RHS_BOUND), e
+    assert np.all(e <= mixed_bound(cfg["polydeg"])), e
+    assert np.all(e[1:4] <= MOMENTUM_BOUND_MACH01), e   # pressure perturbation form
     assert s.check() == 0
 
 
@@ -51,7 +66,7 @@ def test_mixed_random_states():
     got = host(s.rhs(dev(u)))
     e = err_v(got, ref, u, 3, 2.0 / 3)
     print("mixed random nodal err_v", e, flush=True)
-    assert np.all(e <= MIXED_RHS_BOUND), e
+    assert np.all(e <= mixed_bound(3)), e
 
 
 def test_mixed_steps_error_against_oracle():
