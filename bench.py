@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DOF-RHS evals/sec (PID) 3D Euler N=3, FP64 vs mixed vs batched, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flops per clock
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -180,15 +181,28 @@ def main():
     avg_ms, launches, kname = prof
     # dominant kernel: fused volume + surface + lift + Jacobian + RK stage update.
     # Algorithmic bytes per node, averaged over the five stages of a step: each stage reads
-    # u and writes k and u; stages 2-5 also read k (first stage: k = dt R), so the five
-    # stages move 3 + 4 * 4 = 19 arrays of 5 float64 = 760 B, 152 B per launch.
-    alg_bytes = 152.0 * nodes
+    # u and writes u; stages 1-4 write k, stages 2-5 read it (the first stage forms k = dt R,
+    # after the last k is dead), so the five stages move 3 + 4 + 4 + 4 + 3 = 18 arrays of 5
+    # float64 = 720 B, 144 B per launch.
+    alg_bytes = 144.0 * nodes
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": stored_traffic("k_stage_tgv32_fp64"),
                 "kernel": kname, "avg_ms": avg_ms, "launches": launches,
                 "alg_bytes_per_launch": alg_bytes}
+    # The same kernel against the FP64 vector peak: FP64 flops per launch from the committed
+    # counter summary (64 lanes x (ADD + MUL + TRANS + 2 FMA) FP64 VALU instructions, masked
+    # lanes included), over this run's live launch time; null once the sources changed.
+    pmc = stored_pmc("k_stage_tgv32_fp64")
+    valu = None
+    if pmc is not None and pmc.get("fp64_flops_per_launch"):
+        tf = pmc["fp64_flops_per_launch"] / (avg_ms * 1e-3) / 1e12
+        valu = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(tf / FP64_VALU_PEAK_TFLOPS, 4),
+                "fp64_flops_per_launch": pmc["fp64_flops_per_launch"],
+                "valu_insts_per_wave": pmc.get("valu_insts_per_wave"),
+                "fp64_share_of_valu_insts": pmc.get("fp64_share_of_valu_insts")}
     _log(f"step: {secs / args.steps * 1e3:.3f} ms/step, {value:.4e} DOF-RHS/s; "
          f"{kname} avg {avg_ms * 1e3:.1f} us")
 
@@ -201,7 +215,7 @@ def main():
                                   "[-pi,pi]^3, EC volume + LLF surface, CK(5,4) RK at CFL 0.5",
                       "elements": s.E, "polydeg": 3, "dof_per_var": nodes,
                       "parallelism": "single GPU"},
-           "pid_s": 1.0 / value, "roofline": roofline,
+           "pid_s": 1.0 / value, "roofline": roofline, "valu_fp64": valu,
            # unique two-point volume fluxes per node and RHS: 3N/2 in 3D (4.5 at N = 3)
            "unique_flux_evals_per_s": value * 1.5 * cfg["polydeg"]}
 
@@ -334,7 +348,7 @@ def bench_density_wave(args):
 def bench_weak(args, volume="weak"):
     """Weak-form DG + HLL on the 32^3 N = 3 TGV (the paper's other measured solver), with the
     line contractions on the VALU ("weak") or on the matrix cores ("weak_mfma"): full RK
-    steps, with the stage kernel's live average and its HBM fraction (same 152 B/node)."""
+    steps, with the stage kernel's live average and its HBM fraction (same 144 B/node)."""
     from paper_2108_06476_amd import dgx, inputs
     cfg = dict(inputs.workload("tgv_32"), volume=volume, surface="hll")
     s = dgx.Solver(**cfg)
@@ -342,7 +356,7 @@ def bench_weak(args, volume="weak"):
     steps = max(5, args.steps // 2)
     secs, prof = time_steps(s, u, steps, 2, profile=True)
     avg_ms = prof[0]
-    gbs = 152.0 * s.num_nodes / (avg_ms * 1e-3) / 1e9
+    gbs = 144.0 * s.num_nodes / (avg_ms * 1e-3) / 1e9
     return {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps,
             "stage_us": round(avg_ms * 1e3, 2), "stage_hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
 
@@ -402,8 +416,8 @@ def bench_mhd(args, name, volume="weak"):
     s.profile_enable(False)
     if s.check():
         raise RuntimeError("non-physical state during the benchmark")
-    # stage traffic: 8 variables, 3 + 4 * 4 arrays per step over 5 stages (as for Euler)
-    gbs = 8 * 8 * 3.8 * s.num_nodes / (avg_ms * 1e-3) / 1e9
+    # stage traffic: 8 variables, 18 arrays per step over 5 stages (as for Euler)
+    gbs = 8 * 8 * 3.6 * s.num_nodes / (avg_ms * 1e-3) / 1e9
     out = {"value": steps * 5 * s.num_nodes / secs, "unit": "DOF-RHS/s", "steps": steps,
            "ms_per_step": secs / steps * 1e3}
     if prof:
@@ -423,16 +437,22 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def stored_traffic(name):
-    """HBM bytes per launch of `name` from the committed counter summary, or None when the
-    kernel sources changed since the counters were taken."""
+def stored_pmc(name):
+    """The committed counter summary of `name`, or None when it is missing or the kernel
+    sources changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"{name}_pmc.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     if rec.get("source_sha256") != kernel_source_hash():
         return None
-    return rec.get("traffic_bytes_per_launch")
+    return rec
+
+
+def stored_traffic(name):
+    """HBM bytes per launch of `name` from the committed counter summary (None as above)."""
+    rec = stored_pmc(name)
+    return None if rec is None else rec.get("traffic_bytes_per_launch")
 
 
 if __name__ == "__main__":

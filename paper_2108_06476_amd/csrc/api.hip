@@ -321,6 +321,7 @@ dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double 
     a.speed = (adaptive && st == 4 && emit) ? h->partial : nullptr;
     a.t0 = t0;
     a.cs = CK_C[st];
+    a.kw = st < 4;
     // stages of one step run back to back unless indicator kernels sit between them
     HIPCHK(h, launch_stage(h, a, EPI_RK, st == 4 || alpha != nullptr));
     cur = 1 - cur;

@@ -151,7 +151,7 @@ dgx_status enqueue_step(dgx_batch b, hipStream_t st, double cfl, bool emit) {
   int cur = 0;
   for (int s = 0; s < 5; ++s) {
     BHIP(b, batch_stage(st, b->bl, b->budget, b->grid, b->prec, EPI_RK, cur, CK_A[s], CK_B[s],
-                        (emit && s == 4) ? 1 : 0));
+                        (emit && s == 4) ? 1 : 0, s < 4));
     cur = 1 - cur;
   }
   return DGX_OK;
@@ -165,7 +165,7 @@ dgx_status enqueue_two_steps(dgx_batch b, hipStream_t st, double cfl) {
   for (int s = 0; s < 10; ++s) {
     if (s == 5) BHIP(b, batch_dt(st, b->desc_d, b->nruns, cfl));
     BHIP(b, batch_stage(st, b->bl, b->budget, b->grid, b->prec, EPI_RK, cur, CK_A[s % 5],
-                        CK_B[s % 5], (s == 4 || s == 9) ? 1 : 0));
+                        CK_B[s % 5], (s == 4 || s == 9) ? 1 : 0, s % 5 < 4));
     cur = 1 - cur;
   }
   return DGX_OK;
@@ -317,7 +317,7 @@ dgx_status dgx_batch_rhs(dgx_batch b, const double* const* u, double* const* du)
     if (u[r] == du[r]) return bfail(b, DGX_EINVAL, "u and du must not overlap");
   dgx_status st = bind(b, const_cast<double* const*>(u), du, nullptr);
   if (st != DGX_OK) return st;
-  BHIP(b, batch_stage(b->stream, b->bl, b->budget, b->grid, b->prec, EPI_RHS, 0, 0.0, 0.0, 0));
+  BHIP(b, batch_stage(b->stream, b->bl, b->budget, b->grid, b->prec, EPI_RHS, 0, 0.0, 0.0, 0, 0));
   return DGX_OK;
 }
 
@@ -346,7 +346,7 @@ dgx_status dgx_batch_tune(dgx_batch b, double* const* u, int32_t budget_ms) {
       bool fail = false;
       for (int rep = 0; rep < 4 && !fail; ++rep) {
         fail |= hipEventRecord(e0, b->stream) != hipSuccess;
-        fail |= batch_stage(b->stream, b->bl, budget, grid, b->prec, EPI_RHS, 0, 0.0, 0.0, 0) != hipSuccess;
+        fail |= batch_stage(b->stream, b->bl, budget, grid, b->prec, EPI_RHS, 0, 0.0, 0.0, 0, 0) != hipSuccess;
         fail |= hipEventRecord(e1, b->stream) != hipSuccess;
         fail |= hipEventSynchronize(e1) != hipSuccess;
         fail |= hipEventElapsedTime(&ms, e0, e1) != hipSuccess;

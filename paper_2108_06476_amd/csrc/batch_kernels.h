@@ -33,9 +33,10 @@ struct BatchLaunch {
 };
 
 // Host launchers (batch_kernels.hip).  budget: threads per block (256 or 512); grid: number
-// of persistent blocks (a multiple of 8).
+// of persistent blocks (a multiple of 8); kw: the RK stage writes k (0 in a step's last
+// stage).
 hipError_t batch_stage(hipStream_t st, const BatchLaunch& b, int budget, int grid, int prec,
-                       int epi, int cur, double A, double B, int emit_speed);
+                       int epi, int cur, double A, double B, int emit_speed, int kw);
 hipError_t batch_maxspeed(hipStream_t st, const BatchLaunch& b, int budget, int grid);
 hipError_t batch_dt(hipStream_t st, const RunDesc* runs, int nruns, double cfl);
 hipError_t batch_copy(hipStream_t st, const RunDesc* runs, int nruns, int64_t max_len);

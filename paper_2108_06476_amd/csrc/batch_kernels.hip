@@ -49,7 +49,8 @@ __device__ __forceinline__ Geom run_geom(const RunDesc& d) {
 
 template <int N, typename RT, int BUDGET, int EPI>
 __device__ __forceinline__ void batch_tile(unsigned char* smem, const double* sT, const RunDesc& d,
-                                           int tile, int cur, double A, double B, int emit) {
+                                           int tile, int cur, double A, double B, int emit,
+                                           int kw) {
   using L = typename StageLdsOf<3, N, VOL_EC, RT, BUDGET>::type;
   StageArgs a;
   a.uin = cur ? d.u2 : d.u;
@@ -63,6 +64,7 @@ __device__ __forceinline__ void batch_tile(unsigned char* smem, const double* sT
   a.B = B;
   a.surf = d.surf;
   a.fvf = SURF_LLF;
+  a.kw = kw;
   stage_tile<3, N, VOL_EC, EPI, RT, BUDGET>(*reinterpret_cast<L*>(smem), sT, a, run_geom(d), tile);
 }
 
@@ -76,7 +78,7 @@ __device__ __forceinline__ void batch_item_tables(const RunDesc& d, double* sT, 
 // live across it against 128 for one item), so the tuner times both.
 template <typename RT, int BUDGET, int EPI, bool PERSIST>
 __global__ __launch_bounds__(BUDGET) void k_batch_stage(BatchLaunch b, int cur, double A, double B,
-                                                        int emit) {
+                                                        int emit, int kw) {
   __shared__ __align__(16) unsigned char smem[BatchSmem<RT, BUDGET>::bytes];
   __shared__ double sT[TAB_SIZE];
   if constexpr (!PERSIST) {
@@ -86,9 +88,9 @@ __global__ __launch_bounds__(BUDGET) void k_batch_stage(BatchLaunch b, int cur, 
     const RunDesc d = b.runs[b.order[ri]];
     const int tile = item - b.prefix[ri];
     batch_item_tables(d, sT, BUDGET);
-    if (d.N == 3) batch_tile<3, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit);
-    else if (d.N == 4) batch_tile<4, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit);
-    else batch_tile<5, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit);
+    if (d.N == 3) batch_tile<3, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit, kw);
+    else if (d.N == 4) batch_tile<4, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit, kw);
+    else batch_tile<5, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit, kw);
   } else {
     int first, end, stride;
     xcd_range(b.total, first, end, stride);
@@ -98,9 +100,9 @@ __global__ __launch_bounds__(BUDGET) void k_batch_stage(BatchLaunch b, int cur, 
       const int tile = item - b.prefix[ri];
       __syncthreads();   // the previous tile is done with the LDS
       batch_item_tables(d, sT, BUDGET);
-      if (d.N == 3) batch_tile<3, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit);
-      else if (d.N == 4) batch_tile<4, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit);
-      else batch_tile<5, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit);
+      if (d.N == 3) batch_tile<3, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit, kw);
+      else if (d.N == 4) batch_tile<4, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit, kw);
+      else batch_tile<5, RT, BUDGET, EPI>(smem, sT, d, tile, cur, A, B, emit, kw);
     }
   }
 }
@@ -192,34 +194,35 @@ int batch_tile_elems(int N, int budget) {
 
 template <typename RT, int BUDGET, bool PERSIST>
 static hipError_t stage_launch(hipStream_t st, const BatchLaunch& b, int grid, int epi, int cur,
-                               double A, double B, int emit) {
+                               double A, double B, int emit, int kw) {
   if (epi == EPI_RK)
     hipLaunchKernelGGL((k_batch_stage<RT, BUDGET, EPI_RK, PERSIST>), dim3(grid), dim3(BUDGET), 0, st,
-                       b, cur, A, B, emit);
+                       b, cur, A, B, emit, kw);
   else
     hipLaunchKernelGGL((k_batch_stage<RT, BUDGET, EPI_RHS, PERSIST>), dim3(grid), dim3(BUDGET), 0, st,
-                       b, cur, A, B, emit);
+                       b, cur, A, B, emit, kw);
   return hipGetLastError();
 }
 
 template <typename RT>
 static hipError_t stage_launch_rt(hipStream_t st, const BatchLaunch& b, int budget, int grid,
-                                  int epi, int cur, double A, double B, int emit) {
+                                  int epi, int cur, double A, double B, int emit,
+                                  int kw) {
   // grid >= items: one block per item; otherwise persistent blocks
   const bool persist = grid < b.total;
   if (budget == 512) {
-    if (persist) return stage_launch<RT, 512, true>(st, b, grid, epi, cur, A, B, emit);
-    return stage_launch<RT, 512, false>(st, b, grid, epi, cur, A, B, emit);
+    if (persist) return stage_launch<RT, 512, true>(st, b, grid, epi, cur, A, B, emit, kw);
+    return stage_launch<RT, 512, false>(st, b, grid, epi, cur, A, B, emit, kw);
   }
-  if (persist) return stage_launch<RT, 256, true>(st, b, grid, epi, cur, A, B, emit);
-  return stage_launch<RT, 256, false>(st, b, grid, epi, cur, A, B, emit);
+  if (persist) return stage_launch<RT, 256, true>(st, b, grid, epi, cur, A, B, emit, kw);
+  return stage_launch<RT, 256, false>(st, b, grid, epi, cur, A, B, emit, kw);
 }
 
 hipError_t batch_stage(hipStream_t st, const BatchLaunch& b, int budget, int grid, int prec,
-                       int epi, int cur, double A, double B, int emit_speed) {
+                       int epi, int cur, double A, double B, int emit_speed, int kw) {
   if (grid % 8 != 0 || grid <= 0) return hipErrorInvalidValue;
-  if (prec == 1) return stage_launch_rt<float>(st, b, budget, grid, epi, cur, A, B, emit_speed);
-  return stage_launch_rt<double>(st, b, budget, grid, epi, cur, A, B, emit_speed);
+  if (prec == 1) return stage_launch_rt<float>(st, b, budget, grid, epi, cur, A, B, emit_speed, kw);
+  return stage_launch_rt<double>(st, b, budget, grid, epi, cur, A, B, emit_speed, kw);
 }
 
 hipError_t batch_maxspeed(hipStream_t st, const BatchLaunch& b, int budget, int grid) {

@@ -458,6 +458,9 @@ struct StageArgs {
   const double* t0 = nullptr;
   double cs = 0.0;
   double t = 0.0;
+  // RK: write k (0 in a step's last stage: k is dead until the next step's first stage,
+  // which does not read it)
+  int kw = 1;
 };
 
 // Weak form: the physical fluxes f^d_v of every node, contracted along the lines.
@@ -572,7 +575,7 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         const size_t pb = (size_t)(own_ix - node) + (size_t)v * ENN;   // uniform plane base
-        a.k[pb + (unsigned)node] = kv[v];
+        if (a.kw) a.k[pb + (unsigned)node] = kv[v];
         un[v] = um[v] + a.B * kv[v];
         a.uout[pb + (unsigned)node] = un[v];
       }
