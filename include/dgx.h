@@ -95,7 +95,10 @@ typedef struct {
 typedef struct dgx_solver *dgx_handle;
 
 /* Create a solver for cfg (host pointer, copied) whose work goes to hip_stream
- * (a hipStream_t; NULL = the null stream).  Allocates the device scratch. */
+ * (a hipStream_t; NULL = the null stream).  Allocates the device scratch (two state-sized
+ * arrays, u2 and k, plus per-element buffers).  Size: fewer than 2^30 elements (the kernels
+ * use 64-bit offsets, so a state may fill most of the device memory); DGX_EUNSUPPORTED
+ * beyond, DGX_ENOMEM when the device memory runs out. */
 dgx_status dgx_create(const dgx_config *cfg, void *hip_stream, dgx_handle *out);
 dgx_status dgx_destroy(dgx_handle h);
 /* Re-target the handle's work to another stream (e.g. the caller's current one). */
@@ -182,7 +185,8 @@ typedef struct {
  * start of each step), dgx_max_dt (dt from sum_i max (|v . Ja^i| + c |Ja^i|)/J),
  * dgx_node_coords (the mapped positions), dgx_check and the profiling calls;
  * dgx_indicator, dgx_rhs_alpha and dgx_integrals return DGX_EUNSUPPORTED on it.
- * Computes the geometry on the device (synchronises the stream once). */
+ * Computes the geometry on the device (synchronises the stream once).  Size: 9 * nodes
+ * below 2^31 (its kernels index the metric arrays in 32 bits), else DGX_EUNSUPPORTED. */
 dgx_status dgx_create_curved(const dgx_curv_config *cfg, void *hip_stream, dgx_handle *out);
 
 /* The geometry of a curvilinear handle: ja [3 (i)][3 (n)][E][n^3] = (J a^i)_n and
@@ -198,7 +202,8 @@ dgx_status dgx_geometry(dgx_handle h, double *ja, double *jac);
  * discretised as phi(u_i) {{B_d}} in the volume and on the faces (surface EC, LLF or HLL;
  * EC everywhere conserves the entropy exactly).  Fast magnetosonic wave speeds.  The handle works
  * with dgx_rhs, dgx_step (dt from sum_d (2/h) max (|v_d| + c_f,d)), dgx_max_dt,
- * dgx_node_coords, dgx_check and the profiling calls; states are [8][E][n^3]. */
+ * dgx_node_coords, dgx_check and the profiling calls; states are [8][E][n^3].  Size:
+ * 8 * nodes below 2^31 (32-bit state offsets), else DGX_EUNSUPPORTED. */
 typedef struct {
   int32_t polydeg;        /* N; compiled for 1..7 */
   int32_t cells;          /* elements per direction */

@@ -417,7 +417,11 @@ dgx_status create_impl(const dgx_config& c, const dgx_curv_config* cv, void* hip
   h->stream = (hipStream_t)hip_stream;
   h->L = L;
   const int64_t nodes = h->E * h->NN;
-  if ((int64_t)(cv ? 9 : h->NV) * nodes >= ((int64_t)1 << 31)) {   // kernels index in 32 bits
+  // The curvilinear and MHD kernels index a whole state (or metric) array in 32 bits; the
+  // Cartesian Euler kernels use 64-bit offsets and only keep the element index in an int.
+  const bool fits = (cv || mhd) ? (int64_t)(cv ? 9 : h->NV) * nodes < ((int64_t)1 << 31)
+                                : h->E < ((int64_t)1 << 30);
+  if (!fits) {
     delete h;
     return DGX_EUNSUPPORTED;
   }

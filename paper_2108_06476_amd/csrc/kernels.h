@@ -70,8 +70,8 @@ __device__ __forceinline__ int64_t neighbour(const Geom& g, int64_t e, int d, in
   return c0 + (int64_t)g.K[0] * (c1 + (int64_t)g.K[1] * c2);
 }
 
-// Element coordinates (32-bit; the library limits nvar * nodes below 2^31) and the periodic
-// face neighbour in a runtime direction d: e + (wrapped c_d +- 1 - c_d) * stride_d.
+// Element coordinates (32-bit: the library keeps the element count below 2^30) and the
+// periodic face neighbour in a runtime direction d: e + (wrapped c_d +- 1 - c_d) * stride_d.
 __device__ __forceinline__ void elem_xyz(const Geom& g, int e, int (&c)[3]) {
   const unsigned q = (unsigned)e / (unsigned)g.K[0];
   c[0] = e - (int)q * g.K[0];
@@ -379,12 +379,13 @@ __device__ __forceinline__ void face_load(const double* __restrict__ u, const Ge
   if (id != 0 && id != N) return;
   const bool plus = (id == N);
   const int oth = plus ? node - N * st : node + N * st;
-  // both neighbours' indices first (uniform when e is), then one per-lane choice
-  const int enbp = elem_nb(g, e, ec, D, 1), enbm = elem_nb(g, e, ec, D, -1);
-  const unsigned off = (unsigned)(plus ? enbp : enbm) * NN + (unsigned)oth;
-  const unsigned ENN = (unsigned)g.E * NN;
+  // both neighbours' nodes first (uniform when e is), then one per-lane choice
+  const double* pp = u + (size_t)elem_nb(g, e, ec, D, 1) * NN;
+  const double* pm = u + (size_t)elem_nb(g, e, ec, D, -1) * NN;
+  const double* ub = plus ? pp : pm;
+  const size_t ENN = (size_t)g.E * NN;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) un[v] = (u + (size_t)v * ENN)[off];
+  for (int v = 0; v < NV; ++v) un[v] = (ub + (size_t)v * ENN)[(unsigned)oth];
 }
 
 template <int DIM, int N, int D>
@@ -549,7 +550,7 @@ __device__ __forceinline__ void weak_dir(const L& s, int base, int node, const d
 template <int DIM, int N, int NV, int EPI, int BUDGET, typename SpeedFn>
 __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArgs& a,
                                                const Geom& g, int le, int node, int e, bool inb,
-                                               bool active, unsigned ENN, unsigned own_ix,
+                                               bool active, size_t ENN, size_t own_ix,
                                                const double (&um)[NV], const double (&R)[NV],
                                                SpeedFn speeds) {
   using S = Shape<DIM, N, BUDGET>;
@@ -641,8 +642,8 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   const bool inb = le < S::NE;
   const bool active = inb && (e < g.E);
   const int base = le * NN;
-  const unsigned ENN = (unsigned)g.E * NN;
-  const unsigned own_ix = (unsigned)e * NN + node;
+  const size_t ENN = (size_t)g.E * NN;
+  const size_t own_ix = (size_t)e * NN + node;
 
   static_assert(sizeof(RT) == 8 || VOL == VOL_EC, "float32 volume fluxes: EC flux differencing only");
   double um[NV];

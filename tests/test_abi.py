@@ -55,6 +55,22 @@ def test_unsupported_config_reported():
     assert L.dgx_create(C.byref(cfg), None, C.byref(h)) == 5
 
 
+def test_size_limits_reported_before_any_allocation():
+    """Cartesian Euler: fewer than 2^30 elements (64-bit state offsets); curvilinear and MHD
+    handles: 9 (metric terms) or 8 values per node times the nodes below 2^31 (32-bit
+    offsets).  The check precedes every device call."""
+    L = dgx.lib()
+    h = C.c_void_p()
+    cfg = dgx.make_config(3, 1, (1024, 1024, 1024), (0, 0, 0), (1, 1, 1))   # 2^30 elements
+    assert L.dgx_create(C.byref(cfg), None, C.byref(h)) == 5 and not h.value
+    cv = dgx.CurvConfig(polydeg=3, cells=256, warp=0.1, gamma=1.4, volume=dgx.VOLUME["ec"],
+                        surface=dgx.SURFACE["llf"], source=0)              # 9 * 2^30 values
+    assert L.dgx_create_curved(C.byref(cv), None, C.byref(h)) == 5 and not h.value
+    mc = dgx.MhdConfig(polydeg=3, cells=256, gamma=5.0 / 3.0, surface=dgx.SURFACE["hll"],
+                       volume=dgx.VOLUME["weak"])                           # 8 * 2^30 values
+    assert L.dgx_create_mhd(C.byref(mc), None, C.byref(h)) == 5 and not h.value
+
+
 def test_null_handle_calls_fail_cleanly():
     L = dgx.lib()
     assert L.dgx_rhs(None, None, None, C.c_double(0.0)) == 1
