@@ -138,6 +138,18 @@ __device__ __forceinline__ int elem_slot() {
   return NN % 64 == 0 ? __builtin_amdgcn_readfirstlane(threadIdx.x / NN) : (int)(threadIdx.x / NN);
 }
 
+// Sum over the 64 lanes of a wave (all active), valid in lane 63: the steps of
+// wave_max_lane63 with additions; lanes that a broadcast leaves out add zero.
+__device__ __forceinline__ double wave_sum_lane63(double x) {
+  x += dpp_f64<0xB1, 0xF>(0.0, x);    // quad_perm [1,0,3,2]
+  x += dpp_f64<0x4E, 0xF>(0.0, x);    // quad_perm [2,3,0,1]
+  x += dpp_f64<0x141, 0xF>(0.0, x);   // row_half_mirror
+  x += dpp_f64<0x140, 0xF>(0.0, x);   // row_mirror
+  x += dpp_f64<0x142, 0xA>(0.0, x);   // row_bcast:15 into rows 1 and 3
+  x += dpp_f64<0x143, 0xC>(0.0, x);   // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
 template <int DIM, int N>
 __device__ __forceinline__ void elem_sync() {
   if constexpr (WaveElem<DIM, N>::value) wave_sync();
@@ -326,16 +338,22 @@ __device__ __forceinline__ void volume_xy_half(const L& s, double* __restrict__ 
 }
 
 // First-order FV on the LGL subcells in direction D with the fv flux (LLF or HLL):
-// acc += -(2/h_d)/w_i (F_{i+1/2} - F_{i-1/2}), element-boundary subcell fluxes zero.
+// acc += -(2/h_d)/w_i (F_{i+1/2} - F_{i-1/2}), element-boundary subcell fluxes zero.  Every
+// subcell face is evaluated once, by its left node (left state: itself), and shared through
+// the element's LDS slot f [NV][NN]: the right node reads it as its F_{i-1/2} (the same
+// arguments in the same order as its own evaluation would take).  Called by every thread of
+// the block (on: this node's element takes part).
 template <int DIM, int N, int D, typename L>
-__device__ __forceinline__ void fv_dir(const L& s, int fvf, int base, int node, const Prim<double>& me,
+__device__ __forceinline__ void fv_dir(const L& s, double* __restrict__ f, int fvf, bool on,
+                                       int base, int node, const Prim<double>& me,
                                        const double (&ume)[DIM + 2], const double* sFV,
                                        double gamma, double (&acc)[DIM + 2]) {
   constexpr int n = N + 1, st = Stride<D, n>::value;
+  constexpr int NN = Shape<DIM, N>::NN;
   const int id = (node / st) % n;
-  double Fp[DIM + 2], Fm[DIM + 2];
+  double Fp[DIM + 2];
 #pragma unroll
-  for (int v = 0; v < DIM + 2; ++v) { Fp[v] = 0.0; Fm[v] = 0.0; }
+  for (int v = 0; v < DIM + 2; ++v) Fp[v] = 0.0;
   auto load = [&](int pn, double (&uq)[DIM + 2], Prim<double>& q) {
 #pragma unroll
     for (int v = 0; v < DIM + 2; ++v) uq[v] = s.u[v][pn];
@@ -347,21 +365,22 @@ __device__ __forceinline__ void fv_dir(const L& s, int fvf, int base, int node, 
     q.beta = s.beta[pn];
     q.c = s.c[pn];
   };
-  if (id < N) {
+  if (on && id < N) {
     double uq[DIM + 2];
     Prim<double> q;
     load(base + node + st, uq, q);
     face_flux<DIM, D>(fvf, ume, me, uq, q, gamma, Fp);
-  }
-  if (id > 0) {
-    double uq[DIM + 2];
-    Prim<double> q;
-    load(base + node - st, uq, q);
-    face_flux<DIM, D>(fvf, uq, q, ume, me, gamma, Fm);
-  }
-  const double c = sFV[D * TMAX + id];
 #pragma unroll
-  for (int v = 0; v < DIM + 2; ++v) acc[v] += c * (Fp[v] - Fm[v]);
+    for (int v = 0; v < DIM + 2; ++v) f[v * NN + node] = Fp[v];
+  }
+  elem_sync<DIM, N>();
+  if (on) {
+    const double c = sFV[D * TMAX + id];
+#pragma unroll
+    for (int v = 0; v < DIM + 2; ++v)
+      acc[v] += c * (Fp[v] - (id > 0 ? f[v * NN + node - st] : 0.0));
+  }
+  elem_sync<DIM, N>();   // read before the next direction writes
 }
 
 // Surface term of one node in direction D: a node with index_D = 0 (N) lies on the
@@ -762,22 +781,31 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     if (active) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] += (RT)x[v * NN + node];
-      if constexpr (VOL == VOL_SHOCKCAP) {
-        const double al = a.alpha[e];
-        if (al != 0.0) {
-          double fv[NV];
+    }
+    if constexpr (VOL == VOL_SHOCKCAP) {
+      // blended subcell FV part: the partner-share slot x is free once every node has read
+      // its shares and holds the shared subcell fluxes; a one-wave element skips it when its
+      // alpha is zero, a block of other shapes when every alpha in it is zero
+      const double al = active ? a.alpha[e] : 0.0;
+      double fv[NV];
 #pragma unroll
-          for (int v = 0; v < NV; ++v) fv[v] = 0.0;
-          fv_dir<DIM, N, 0>(s, a.fvf, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
-          fv_dir<DIM, N, 1>(s, a.fvf, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
-          if constexpr (DIM == 3) fv_dir<DIM, N, 2>(s, a.fvf, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
+      for (int v = 0; v < NV; ++v) fv[v] = 0.0;
+      const bool any = WaveElem<DIM, N>::value ? (al != 0.0) : (__syncthreads_or(al != 0.0) != 0);
+      if (any) {
+        const bool on = active && al != 0.0;
+        elem_sync<DIM, N>();
+        fv_dir<DIM, N, 0>(s, x, a.fvf, on, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
+        fv_dir<DIM, N, 1>(s, x, a.fvf, on, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
+        if constexpr (DIM == 3)
+          fv_dir<DIM, N, 2>(s, x, a.fvf, on, base, node, qd, um, sT + TAB_FV, g.gamma, fv);
+      }
+      if (active) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) R[v] += (1.0 - al) * (double)acc[v] + al * fv[v];
-        } else {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) R[v] += (double)acc[v];
-        }
-      } else if constexpr (SEED) {
+        for (int v = 0; v < NV; ++v)
+          R[v] += al != 0.0 ? (1.0 - al) * (double)acc[v] + al * fv[v] : (double)acc[v];
+      }
+    } else if (active) {
+      if constexpr (SEED) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) R[v] = (double)acc[v];
       } else {
@@ -820,14 +848,15 @@ void k_stage(StageArgs a, Geom g) {
 template <int DIM, int N>
 __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_indicator(
     const double* __restrict__ u, double* __restrict__ alpha_raw, double* __restrict__ energy,
-    Geom g, double alpha_min, double alpha_max) {
+    Geom g, double alpha_min, double alpha_max, double thr, double sharp) {
   using S = Shape<DIM, N>;
   constexpr int NN = S::NN, n = S::n;
-  __shared__ double sa[S::NE * NN], sb[S::NE * NN];
+  constexpr bool WAVE = WaveElem<DIM, N>::value;
+  __shared__ double sa[S::NE * NN], sb[S::NE * NN], sc[WAVE ? 1 : S::NE * NN];
   __shared__ double sV[TMAX * TMAX];
   for (int i = threadIdx.x; i < TMAX * TMAX; i += blockDim.x) sV[i] = g.tab[TAB_VINV + i];
-  const int le = threadIdx.x / NN;
-  const int node = threadIdx.x - le * NN;
+  const int le = elem_slot<NN>();
+  const int node = (int)(threadIdx.x % (unsigned)NN);
   const int64_t e = (int64_t)blockIdx.x * S::NE + le;
   const bool active = (le < S::NE) && (e < g.E);
   const int base = le * NN;
@@ -840,7 +869,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_indicator(
     if (!cons_to_prim<DIM>(um, g.gamma, q)) *g.flag = 1;
     sa[base + node] = q.rho * q.p;
   }
-  __syncthreads();
+  __syncthreads();   // V^-1 and the nodal values
   double* in = sa;
   double* out = sb;
 #pragma unroll
@@ -854,30 +883,59 @@ __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_indicator(
       for (int m = 0; m < n; ++m) acc += sV[id * TMAX + m] * in[nb + m * st];
       out[base + node] = acc;
     }
-    __syncthreads();
+    elem_sync<DIM, N>();
     double* t = in;
     in = out;
     out = t;
   }
-  // in[] holds the modal coefficients; square them
-  if (active) in[base + node] = in[base + node] * in[base + node];
-  __syncthreads();
-  if (active && node == 0) {
-    double Et = 0.0, E1 = 0.0, E2 = 0.0;
-    for (int nd = 0; nd < NN; ++nd) {
-      const int i = nd % n, j = (nd / n) % n, k = DIM == 3 ? nd / (n * n) : 0;
-      const int mx = max(i, max(j, k));
-      const double c = in[base + nd];
-      Et += c;
-      if (mx <= N - 1) E1 += c;
-      if (mx <= N - 2) E2 += c;
+  // in[] holds the modal coefficients; the energy of all modes and of the index cubes
+  // [0, N-1]^d and [0, N-2]^d, summed over the element's nodes
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+  if (active) {
+    const int i = node % n, j = (node / n) % n, k = DIM == 3 ? node / (n * n) : 0;
+    const int mx = max(i, max(j, k));
+    const double c = in[base + node] * in[base + node];
+    t0 = c;
+    t1 = mx <= N - 1 ? c : 0.0;
+    t2 = mx <= N - 2 ? c : 0.0;
+  }
+  int last = 0;   // the node that holds the sums
+  if constexpr (WAVE) {
+    if (active) {   // uniform per wave: the element is the wave
+      t0 = wave_sum_lane63(t0);
+      t1 = wave_sum_lane63(t1);
+      t2 = wave_sum_lane63(t2);
     }
-    const double r1 = Et != 0.0 ? (Et - E1) / Et : 0.0;
-    const double r2 = E1 != 0.0 ? (E1 - E2) / E1 : 0.0;
+    last = NN - 1;
+  } else {
+    constexpr int P2 = NN <= 4 ? 4 : NN <= 16 ? 16 : NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
+    double* a0 = out;   // free: the transform's scratch
+    elem_sync<DIM, N>();
+    if (le < S::NE) {
+      a0[base + node] = t0;
+      in[base + node] = t1;
+      sc[base + node] = t2;
+    }
+    __syncthreads();
+    for (int hh = P2 / 2; hh > 0; hh >>= 1) {
+      if (le < S::NE && node < hh && node + hh < NN) {
+        a0[base + node] += a0[base + node + hh];
+        in[base + node] += in[base + node + hh];
+        sc[base + node] += sc[base + node + hh];
+      }
+      __syncthreads();
+    }
+    if (le < S::NE) {
+      t0 = a0[base];
+      t1 = in[base];
+      t2 = sc[base];
+    }
+  }
+  if (active && node == last) {
+    const double r1 = t0 != 0.0 ? (t0 - t1) / t0 : 0.0;
+    const double r2 = t1 != 0.0 ? (t1 - t2) / t1 : 0.0;
     const double en = fmax(r1, r2);
-    const double T = 0.5 * pow(10.0, -1.8 * pow((double)(N + 1), 0.25));
-    const double sg = log((1.0 - 0.0001) / 0.0001);
-    double al = 1.0 / (1.0 + exp(-(sg / T) * (en - T)));
+    double al = 1.0 / (1.0 + exp(-sharp * (en - thr)));
     if (al < alpha_min) al = 0.0;
     else if (al > 1.0 - alpha_min) al = 1.0;
     al = fmin(al, alpha_max);

@@ -1,5 +1,6 @@
 // registry.h -- host launchers of the templated kernels, one table per (dim, polydeg).
 #pragma once
+#include <cmath>
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -80,8 +81,11 @@ struct Launch {
 
   static hipError_t indicator(hipStream_t st, const double* u, double* ar, double* en,
                               const Geom& g, double amin, double amax) {
+    // threshold T = 0.5 10^(-1.8 (N+1)^(1/4)) and sharpness ln((1 - 1e-4)/1e-4) / T
+    const double thr = 0.5 * std::pow(10.0, -1.8 * std::pow((double)(N + 1), 0.25));
+    const double sharp = std::log((1.0 - 0.0001) / 0.0001) / thr;
     hipLaunchKernelGGL((k_indicator<DIM, N>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st, u, ar,
-                       en, g, amin, amax);
+                       en, g, amin, amax, thr, sharp);
     return hipGetLastError();
   }
 
