@@ -228,8 +228,9 @@ __device__ __forceinline__ MhdNode mhd_node(const MhdPrim& q) {
 template <int D>
 __device__ __forceinline__ void mhd_ec_flux(const MhdNode& L, const MhdNode& R, double inv_gm1,
                                             double (&f)[8]) {
-  const double rho_ln = ln_mean(L.rho, R.rho);
-  const double ibeta = inv_ln_mean(L.beta, R.beta);
+  // the near-equal series and the logarithm only: this kernel is short of registers
+  const double rho_ln = ln_mean<false>(L.rho, R.rho);
+  const double ibeta = inv_ln_mean<false>(L.beta, R.beta);
   const double ba = 0.5 * (L.beta + R.beta);
   const double iba = rcp_nr(ba);
   double va[3], Ba[3];

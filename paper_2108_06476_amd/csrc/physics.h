@@ -48,27 +48,43 @@ __device__ __forceinline__ double sqrt_pos(double x) {
   return fma(d, h, g);
 }
 
+// artanh(z)/z = sum_k z^(2k)/(2k+1), k = 0..15: below z^2 = 0.1 the truncation is under
+// 3.3e-18 relative (the first omitted term z^32/33 over 1 - z^2).
+__device__ __forceinline__ double artanh_over_z(double z2) {
+  double p = 1.0 / 31.0;
+#pragma unroll
+  for (int k = 14; k >= 0; --k) p = fma(p, z2, 1.0 / (2 * k + 1));
+  return p;
+}
+
 // Logarithmic mean {{a}}_ln = (b - a)/(ln b - ln a) and its reciprocal.  With
 // z = (b - a)/(b + a), ln(b/a) = 2 artanh z, so {{a}}_ln = (a + b)/2 * z/artanh(z) and
 // 1/{{a}}_ln = 2/(a + b) * artanh(z)/z.  Below z^2 = 1e-4 (the threshold of the efficiency
 // reference the paper cites, Section 3.2) both use their Taylor series in z^2 to z^6
-// (truncation below 1.2e-17), so one reciprocal of a + b serves the whole evaluation.
+// (truncation below 1.2e-17), so one reciprocal of a + b serves the whole evaluation; up to
+// z^2 = 0.1 (states within a factor 1.9) the 16-term series of artanh(z)/z replaces the
+// logarithm and its two divisions (MID; a kernel that never meets such jumps and is short of
+// registers leaves it out); beyond it the logarithm.
+template <bool MID = true>
 __device__ __forceinline__ double ln_mean(double a, double b) {
   const double s = a + b, d = b - a;
   const double r = rcp_nr1(s);   // only z is formed from it
   const double z = d * r, z2 = z * z;
   if (z2 < 1.0e-4)
     return 0.5 * s * (1.0 + z2 * (-1.0 / 3.0 + z2 * (-4.0 / 45.0 + z2 * (-44.0 / 945.0))));
+  if (MID && z2 < 0.1) return 0.5 * s * rcp_nr(artanh_over_z(z2));
   const double hi = fmax(a, b), lo = fmin(a, b);   // symmetric in (a, b), bit for bit
   return (hi - lo) / log(hi / lo);
 }
 
+template <bool MID = true>
 __device__ __forceinline__ double inv_ln_mean(double a, double b) {
   const double s = a + b, d = b - a;
   const double r = rcp_nr(s);
   const double z = d * r, z2 = z * z;
   if (z2 < 1.0e-4)
     return 2.0 * r * (1.0 + z2 * (1.0 / 3.0 + z2 * (1.0 / 5.0 + z2 * (1.0 / 7.0))));
+  if (MID && z2 < 0.1) return 2.0 * r * artanh_over_z(z2);
   const double hi = fmax(a, b), lo = fmin(a, b);
   return log(hi / lo) / (hi - lo);
 }
