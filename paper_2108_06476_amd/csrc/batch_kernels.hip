@@ -73,11 +73,12 @@ __device__ __forceinline__ void batch_item_tables(const RunDesc& d, double* sT, 
 }
 
 // One launch covers every work item of every run.  PERSIST = false: one block per item
-// (block b takes item xcd_tile(b)); PERSIST = true: a fixed grid whose blocks loop over
+// (block b takes item xcd_tile(b)), asked for 4 waves per SIMD (the float32 body would
+// otherwise take 130 VGPRs and 3); PERSIST = true: a fixed grid whose blocks loop over
 // XCD-contiguous item ranges.  The loop costs registers (the compiler keeps ~200 VGPRs
 // live across it against 128 for one item), so the tuner times both.
 template <typename RT, int BUDGET, int EPI, bool PERSIST>
-__global__ __launch_bounds__(BUDGET) void k_batch_stage(BatchLaunch b, int cur, double A, double B,
+__global__ __launch_bounds__(BUDGET, PERSIST ? 1 : 4) void k_batch_stage(BatchLaunch b, int cur, double A, double B,
                                                         int emit, int kw) {
   __shared__ __align__(16) unsigned char smem[BatchSmem<RT, BUDGET>::bytes];
   __shared__ double sT[TAB_SIZE];
