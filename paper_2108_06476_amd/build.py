@@ -2,11 +2,14 @@
 
 Every translation unit under ``csrc/`` is compiled on its own (in parallel) and linked
 into one shared library next to this file.  Packed-FP32 instruction selection is
-disabled for all device code.
+disabled for all device code.  The compiler's per-kernel resource report (VGPRs, spills,
+LDS, occupancy) is kept in ``_build/resources.json``.
 """
 import concurrent.futures as cf
 import glob
+import json
 import os
+import re
 import subprocess
 import sys
 
@@ -16,9 +19,30 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdgx.so")
 ARCH = os.environ.get("DGX_OFFLOAD_ARCH", "gfx950")
 
+RESOURCES = os.path.join(OBJ, "resources.json")
+
 CXXFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-Rpass-analysis=kernel-resource-usage",
             "-Wno-unused-command-line-argument", "-I", os.path.join(HERE, "..", "include")]
+
+_REMARK = re.compile(r"remark:\s+(Function Name|VGPRs|AGPRs|VGPRs Spill|ScratchSize \[bytes/lane\]|"
+                     r"Occupancy \[waves/SIMD\]|LDS Size \[bytes/block\]): (\S+)")
+_KEYS = {"VGPRs": "vgprs", "AGPRs": "agprs", "VGPRs Spill": "vgpr_spill",
+         "ScratchSize [bytes/lane]": "scratch", "Occupancy [waves/SIMD]": "occupancy",
+         "LDS Size [bytes/block]": "lds"}
+
+
+def _resources(text):
+    """Per-kernel resource usage from hipcc's kernel-resource-usage remarks."""
+    out, cur = {}, None
+    for m in _REMARK.finditer(text):
+        key, val = m.group(1), m.group(2)
+        if key == "Function Name":
+            cur = out.setdefault(val, {})
+        elif cur is not None:
+            cur[_KEYS[key]] = int(val)
+    return out
 
 
 def _compile(src, verbose):
@@ -28,12 +52,13 @@ def _compile(src, verbose):
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
-                    if "packed-fp32-ops" not in l and "not a recognized feature" not in l)
+                    if "packed-fp32-ops" not in l and "not a recognized feature" not in l
+                    and "kernel-resource-usage" not in l)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{msg}")
     if msg.strip() and verbose:
         print(msg)
-    return obj
+    return obj, _resources(r.stderr)
 
 
 def build(verbose=False, jobs=None):
@@ -41,7 +66,13 @@ def build(verbose=False, jobs=None):
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
     jobs = jobs or min(8, os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
+        done = list(ex.map(lambda s: _compile(s, verbose), srcs))
+    objs = [o for o, _ in done]
+    res = {}
+    for _, r in done:
+        res.update(r)
+    with open(RESOURCES, "w") as f:
+        json.dump(res, f, indent=0, sort_keys=True)
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
