@@ -183,8 +183,10 @@ def random_smooth(xyz, seed, amp=0.2, vamp=0.5, nmodes=4, periods=None):
 
 def random_nodal(shape_nodes, dim, seed, rho_range=(0.5, 1.5), p_range=(0.5, 1.5), vamp=1.0,
                  gamma=GAMMA):
-    """Non-smooth random state: independent uniform rho, p and v at every node; exercises
-    both branches of the logarithmic mean and both signs of every wave speed."""
+    """Non-smooth random state: independent uniform rho, p and v at every node.  Neighbour
+    ratios up to 3 put z^2 = ((b - a)/(b + a))^2 across [0, 0.25), so every branch of the
+    logarithmic mean (near-equal series, longer series, logarithm) and both signs of every
+    wave speed occur."""
     rng = np.random.default_rng(seed)
     rho = rng.uniform(*rho_range, size=shape_nodes)
     p = rng.uniform(*p_range, size=shape_nodes)
