@@ -294,9 +294,11 @@ dgx_status enqueue_rhs(dgx_handle h, const double* u, double* du, const double* 
 
 // One RK step on h->stream: dt (adaptive: from the partials in h->partial), then the five
 // stages; emit: the last stage writes the next step's partials.  cur: which of buf holds
-// the state (toggled by every stage).
+// the state (toggled by every stage).  Shock capturing: every stage writes the raw
+// indicator of its output state, so a stage only smooths it, except the first stage of a
+// step with fresh set (the first of a call or of a captured graph), which computes it.
 dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double cfl,
-                        double dt_fixed, double* t, bool emit) {
+                        double dt_fixed, double* t, bool emit, bool fresh) {
   const bool adaptive = cfl > 0.0;
   double* t0 = h->g.source ? h->t0 : nullptr;   // step start time for the stage times
   if (adaptive) {
@@ -310,11 +312,21 @@ dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double 
     const double* uin = buf[cur];
     const double* alpha = nullptr;
     if (h->cfg.volume == DGX_VOL_SHOCKCAP_HG && !h->curved && !h->mhd) {
-      dgx_status r = enqueue_indicator(h, uin, h->alpha, h->alpha_raw, nullptr);
-      if (r != DGX_OK) return r;
+      if (st == 0 && fresh) {
+        dgx_status r = enqueue_indicator(h, uin, h->alpha, h->alpha_raw, nullptr);
+        if (r != DGX_OK) return r;
+      } else {
+        HIPCHK(h, h->L->smooth(h->stream, h->alpha_raw, h->alpha, h->g, h->cfg.alpha_smooth));
+      }
       alpha = h->alpha;
     }
     StageArgs a = stage_args(h, uin, alpha);
+    if (alpha) {
+      a.alpha_next = h->alpha_raw;
+      indicator_constants(h->N, a.ind_thr, a.ind_sharp);
+      a.ind_amin = h->cfg.alpha_min;
+      a.ind_amax = h->cfg.alpha_max;
+    }
     a.uout = buf[1 - cur];
     a.A = CK_A[st];
     a.B = CK_B[st];
@@ -349,8 +361,8 @@ dgx_status ensure_step_graph(dgx_handle h, double* u, double cfl, double dt_fixe
   h->stream = h->cap;
   double* buf[2] = {u, h->u2};
   int cur = 0;
-  dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, true);
-  if (st == DGX_OK) st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, true);
+  dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, true, true);
+  if (st == DGX_OK) st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, true, false);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(h->cap, &g);
   h->stream = user;
@@ -676,8 +688,8 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
     if (st != DGX_OK) return st;
     for (; s + 2 <= nsteps; s += 2) HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
   }
-  for (; s < nsteps; ++s) {
-    dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, s + 1 < nsteps);
+  for (const int s0 = s; s < nsteps; ++s) {
+    dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, s + 1 < nsteps, s == s0);
     if (st != DGX_OK) return st;
   }
   if (cur != 0) {

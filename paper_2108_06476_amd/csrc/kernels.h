@@ -481,6 +481,10 @@ struct StageArgs {
   // RK: write k (0 in a step's last stage: k is dead until the next step's first stage,
   // which does not read it)
   int kw = 1;
+  // shock capturing, RK: the raw indicator of the stage's output state (nullptr: skip) and
+  // its constants (threshold, sharpness, alpha_min, alpha_max)
+  double* alpha_next = nullptr;
+  double ind_thr = 0.0, ind_sharp = 0.0, ind_amin = 0.0, ind_amax = 0.0;
 };
 
 // Weak form: the physical fluxes f^d_v of every node, contracted along the lines.
@@ -571,7 +575,7 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
                                                const Geom& g, int le, int node, int e, bool inb,
                                                bool active, size_t ENN, size_t own_ix,
                                                const double (&um)[NV], const double (&R)[NV],
-                                               SpeedFn speeds) {
+                                               SpeedFn speeds, double* un_out = nullptr) {
   using S = Shape<DIM, N, BUDGET>;
   using SS = StageShape<DIM, N, double, BUDGET>;
   constexpr int NN = S::NN;
@@ -598,6 +602,7 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
         if (a.kw) a.k[pb + (unsigned)node] = kv[v];
         un[v] = um[v] + a.B * kv[v];
         a.uout[pb + (unsigned)node] = un[v];
+        if (un_out) un_out[v] = un[v];
       }
     }
     if (a.speed != nullptr) {
@@ -642,6 +647,91 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
         }
       }
     }
+  }
+}
+
+// The indicator of one element from q = rho p at its nodes: w0, w1, w2 are NN-double LDS
+// scratch arrays of the element (w0 holds q on entry), sV the LDS V^-1 table.  Called by
+// every thread of the block (inb: the thread has an element slot; active: its element
+// exists); a one-wave element uses wave-level ordering, other shapes block barriers.
+template <int DIM, int N>
+__device__ __forceinline__ void indicator_elem(double* w0, double* w1, double* w2,
+                                               const double* sV, int node, bool inb, bool active,
+                                               double thr, double sharp, double alpha_min,
+                                               double alpha_max, double* __restrict__ alpha_raw,
+                                               double* __restrict__ energy, int64_t e) {
+  constexpr int NN = Shape<DIM, N>::NN, n = N + 1;
+  constexpr bool WAVE = WaveElem<DIM, N>::value;
+  elem_sync<DIM, N>();   // q visible
+  double* in = w0;
+  double* out = w1;
+#pragma unroll
+  for (int D = 0; D < DIM; ++D) {
+    const int st = D == 0 ? 1 : (D == 1 ? n : n * n);
+    if (active) {
+      const int id = (node / st) % n;
+      const int nb = node - id * st;
+      double acc = 0.0;
+#pragma unroll
+      for (int m = 0; m < n; ++m) acc += sV[id * TMAX + m] * in[nb + m * st];
+      out[node] = acc;
+    }
+    elem_sync<DIM, N>();
+    double* t = in;
+    in = out;
+    out = t;
+  }
+  // in[] holds the modal coefficients; the energy of all modes and of the index cubes
+  // [0, N-1]^d and [0, N-2]^d, summed over the element's nodes
+  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
+  if (active) {
+    const int i = node % n, j = (node / n) % n, k = DIM == 3 ? node / (n * n) : 0;
+    const int mx = max(i, max(j, k));
+    const double c = in[node] * in[node];
+    t0 = c;
+    t1 = mx <= N - 1 ? c : 0.0;
+    t2 = mx <= N - 2 ? c : 0.0;
+  }
+  int last = 0;   // the node that holds the sums
+  if constexpr (WAVE) {
+    if (active) {   // uniform per wave: the element is the wave
+      t0 = wave_sum_lane63(t0);
+      t1 = wave_sum_lane63(t1);
+      t2 = wave_sum_lane63(t2);
+    }
+    last = NN - 1;
+  } else {
+    constexpr int P2 = NN <= 4 ? 4 : NN <= 16 ? 16 : NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
+    double* a0 = out;   // free: the transform's scratch
+    elem_sync<DIM, N>();
+    if (inb) {
+      a0[node] = t0;
+      in[node] = t1;
+      w2[node] = t2;
+    }
+    __syncthreads();
+    for (int hh = P2 / 2; hh > 0; hh >>= 1) {
+      if (inb && node < hh && node + hh < NN) {
+        a0[node] += a0[node + hh];
+        in[node] += in[node + hh];
+        w2[node] += w2[node + hh];
+      }
+      __syncthreads();
+    }
+    t0 = a0[0];
+    t1 = in[0];
+    t2 = w2[0];
+  }
+  if (active && node == last) {
+    const double r1 = t0 != 0.0 ? (t0 - t1) / t0 : 0.0;
+    const double r2 = t1 != 0.0 ? (t1 - t2) / t1 : 0.0;
+    const double en = fmax(r1, r2);
+    double al = 1.0 / (1.0 + exp(-sharp * (en - thr)));
+    if (al < alpha_min) al = 0.0;
+    else if (al > 1.0 - alpha_min) al = 1.0;
+    al = fmin(al, alpha_max);
+    alpha_raw[e] = al;
+    if (energy) energy[e] = en;
   }
 }
 
@@ -816,6 +906,8 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   }
 
   // ---- epilogue
+  constexpr bool IND = VOL == VOL_SHOCKCAP && EPI == EPI_RK;   // indicator of the output
+  double un[NV];
   stage_epilogue<DIM, N, NV, EPI, BUDGET>(
       s.xb, a, g, le, node, e, inb, active, ENN, own_ix, um, R,
       [&](const double (&un)[NV], double (&ls)[DIM]) {
@@ -824,7 +916,23 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
 #pragma unroll
         for (int d = 0; d < DIM; ++d) ls[d] = sT[TAB_JAC + d] * (fabs(q.v[d]) + q.c);
         return ok;
-      });
+      },
+      IND ? un : nullptr);
+  // shock capturing: the raw indicator of the state just written, for the next stage (the
+  // computation of k_indicator on the same values, in the element's LDS slot)
+  if constexpr (IND) {
+    if (a.alpha_next) {   // uniform
+      double* w = reinterpret_cast<double*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);
+      elem_sync<DIM, N>();   // the epilogue is done with the slot
+      if (active) {
+        Prim<double> q;
+        if (!cons_to_prim<DIM>(un, g.gamma, q)) *g.flag = 1;
+        w[node] = q.rho * q.p;
+      }
+      indicator_elem<DIM, N>(w, w + NN, w + 2 * NN, sT + TAB_VINV, node, inb, active, a.ind_thr,
+                             a.ind_sharp, a.ind_amin, a.ind_amax, a.alpha_next, nullptr, e);
+    }
+  }
 }
 
 // The matrix-core variant asks for 4 waves per SIMD (its accumulators would otherwise push
@@ -850,16 +958,15 @@ __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_indicator(
     const double* __restrict__ u, double* __restrict__ alpha_raw, double* __restrict__ energy,
     Geom g, double alpha_min, double alpha_max, double thr, double sharp) {
   using S = Shape<DIM, N>;
-  constexpr int NN = S::NN, n = S::n;
-  constexpr bool WAVE = WaveElem<DIM, N>::value;
-  __shared__ double sa[S::NE * NN], sb[S::NE * NN], sc[WAVE ? 1 : S::NE * NN];
+  constexpr int NN = S::NN;
+  __shared__ double sa[S::NE * NN], sb[S::NE * NN], sc[S::NE * NN];
   __shared__ double sV[TMAX * TMAX];
   for (int i = threadIdx.x; i < TMAX * TMAX; i += blockDim.x) sV[i] = g.tab[TAB_VINV + i];
   const int le = elem_slot<NN>();
   const int node = (int)(threadIdx.x % (unsigned)NN);
   const int64_t e = (int64_t)blockIdx.x * S::NE + le;
   const bool active = (le < S::NE) && (e < g.E);
-  const int base = le * NN;
+  const int base = (le < S::NE ? le : 0) * NN;
   const int64_t ENN = g.E * NN;
   if (active) {
     double um[S::NV];
@@ -869,79 +976,9 @@ __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_indicator(
     if (!cons_to_prim<DIM>(um, g.gamma, q)) *g.flag = 1;
     sa[base + node] = q.rho * q.p;
   }
-  __syncthreads();   // V^-1 and the nodal values
-  double* in = sa;
-  double* out = sb;
-#pragma unroll
-  for (int D = 0; D < DIM; ++D) {
-    const int st = D == 0 ? 1 : (D == 1 ? n : n * n);
-    if (active) {
-      const int id = (node / st) % n;
-      const int nb = base + node - id * st;
-      double acc = 0.0;
-#pragma unroll
-      for (int m = 0; m < n; ++m) acc += sV[id * TMAX + m] * in[nb + m * st];
-      out[base + node] = acc;
-    }
-    elem_sync<DIM, N>();
-    double* t = in;
-    in = out;
-    out = t;
-  }
-  // in[] holds the modal coefficients; the energy of all modes and of the index cubes
-  // [0, N-1]^d and [0, N-2]^d, summed over the element's nodes
-  double t0 = 0.0, t1 = 0.0, t2 = 0.0;
-  if (active) {
-    const int i = node % n, j = (node / n) % n, k = DIM == 3 ? node / (n * n) : 0;
-    const int mx = max(i, max(j, k));
-    const double c = in[base + node] * in[base + node];
-    t0 = c;
-    t1 = mx <= N - 1 ? c : 0.0;
-    t2 = mx <= N - 2 ? c : 0.0;
-  }
-  int last = 0;   // the node that holds the sums
-  if constexpr (WAVE) {
-    if (active) {   // uniform per wave: the element is the wave
-      t0 = wave_sum_lane63(t0);
-      t1 = wave_sum_lane63(t1);
-      t2 = wave_sum_lane63(t2);
-    }
-    last = NN - 1;
-  } else {
-    constexpr int P2 = NN <= 4 ? 4 : NN <= 16 ? 16 : NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
-    double* a0 = out;   // free: the transform's scratch
-    elem_sync<DIM, N>();
-    if (le < S::NE) {
-      a0[base + node] = t0;
-      in[base + node] = t1;
-      sc[base + node] = t2;
-    }
-    __syncthreads();
-    for (int hh = P2 / 2; hh > 0; hh >>= 1) {
-      if (le < S::NE && node < hh && node + hh < NN) {
-        a0[base + node] += a0[base + node + hh];
-        in[base + node] += in[base + node + hh];
-        sc[base + node] += sc[base + node + hh];
-      }
-      __syncthreads();
-    }
-    if (le < S::NE) {
-      t0 = a0[base];
-      t1 = in[base];
-      t2 = sc[base];
-    }
-  }
-  if (active && node == last) {
-    const double r1 = t0 != 0.0 ? (t0 - t1) / t0 : 0.0;
-    const double r2 = t1 != 0.0 ? (t1 - t2) / t1 : 0.0;
-    const double en = fmax(r1, r2);
-    double al = 1.0 / (1.0 + exp(-sharp * (en - thr)));
-    if (al < alpha_min) al = 0.0;
-    else if (al > 1.0 - alpha_min) al = 1.0;
-    al = fmin(al, alpha_max);
-    alpha_raw[e] = al;
-    if (energy) energy[e] = en;
-  }
+  __syncthreads();   // V^-1
+  indicator_elem<DIM, N>(sa + base, sb + base, sc + base, sV, node, le < S::NE, active, thr,
+                         sharp, alpha_min, alpha_max, alpha_raw, energy, e);
 }
 
 // alpha_e = max(alpha_raw_e, max over face neighbours alpha_raw_nb / 2)

@@ -11,6 +11,13 @@ namespace dgx {
 
 enum { PREC_FP64 = 0, PREC_MIXED = 1 };
 
+// Hennemann-Gassner constants of polydeg N: threshold T = 0.5 10^(-1.8 (N+1)^(1/4)) and
+// sharpness ln((1 - 1e-4)/1e-4) / T.
+inline void indicator_constants(int N, double& thr, double& sharp) {
+  thr = 0.5 * std::pow(10.0, -1.8 * std::pow((double)(N + 1), 0.25));
+  sharp = std::log((1.0 - 0.0001) / 0.0001) / thr;
+}
+
 struct Launchers {
   int threads = 0;   // block size of the element-tiled kernels
   int ne = 0;        // elements per block
@@ -81,9 +88,8 @@ struct Launch {
 
   static hipError_t indicator(hipStream_t st, const double* u, double* ar, double* en,
                               const Geom& g, double amin, double amax) {
-    // threshold T = 0.5 10^(-1.8 (N+1)^(1/4)) and sharpness ln((1 - 1e-4)/1e-4) / T
-    const double thr = 0.5 * std::pow(10.0, -1.8 * std::pow((double)(N + 1), 0.25));
-    const double sharp = std::log((1.0 - 0.0001) / 0.0001) / thr;
+    double thr, sharp;
+    indicator_constants(N, thr, sharp);
     hipLaunchKernelGGL((k_indicator<DIM, N>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st, u, ar,
                        en, g, amin, amax, thr, sharp);
     return hipGetLastError();
