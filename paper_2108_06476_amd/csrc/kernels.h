@@ -219,6 +219,13 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// The EC volume stages the nodes' velocities halved (exact), which saves multiplications in
+// the pair flux (ec_flux_h); the blended FV and central forms read them whole.
+template <int VOL>
+struct StagedHalfV {
+  static constexpr bool value = VOL == VOL_EC;
+};
+
 // Unique pairs along direction D.  In round r every node i pairs with i + r (mod n) and
 // evaluates the symmetric two-point flux once: it keeps S_{i,m} f and adds S_{m,i} f into
 // node m's LDS accumulator x (read back once after all directions).  Rounds r = 1..(n-1)/2
@@ -230,7 +237,7 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
 template <int DIM, int N, int D, int VOL, typename RT, bool HALF, typename L>
 __device__ __forceinline__ void volume_dir(const L& s, double* __restrict__ x /* element slot */,
                                            bool on, int base,
-                                           int node, const Prim<RT>& me,
+                                           int node, const Prim<RT>& me, const RT (&hme)[3],
                                            const double (&ume)[DIM + 2], const double* sS,
                                            RT inv_gm1, RT pref, RT (&acc)[DIM + 2]) {
   constexpr int n = N + 1, st = Stride<D, n>::value;
@@ -271,7 +278,9 @@ __device__ __forceinline__ void volume_dir(const L& s, double* __restrict__ x /*
 #pragma unroll
         for (int v = 0; v < DIM + 2; ++v) f[v] = (RT)fd[v];
       } else if constexpr (sizeof(RT) == 4) {
-        ec_flux_pp<DIM, D>(me, q, inv_gm1, pref, f);
+        ec_flux_pp<DIM, D>(me, hme, q, inv_gm1, pref, f);
+      } else if constexpr (StagedHalfV<VOL>::value) {
+        ec_flux_h<DIM, D, RT>(me, hme, q, inv_gm1, f);
       } else {
         ec_flux<DIM, D, RT>(me, q, inv_gm1, f);
       }
@@ -294,11 +303,11 @@ __device__ __forceinline__ void volume_dir(const L& s, double* __restrict__ x /*
 // its x pair and the others their y pair: 64 of 64 lanes busy where the two half rounds
 // kept 32.  The y flux is the x flux of the states with v_x and v_y exchanged, its momentum
 // components exchanged back.
-template <int DIM, int N, typename RT, typename L>
+template <int DIM, int N, int VOL, typename RT, typename L>
 __device__ __forceinline__ void volume_xy_half(const L& s, double* __restrict__ x, bool on,
                                                int base, int node, const Prim<RT>& me,
-                                               const double* sS, RT inv_gm1, RT pref,
-                                               RT (&acc)[DIM + 2]) {
+                                               const RT (&hme)[3], const double* sS,
+                                               RT inv_gm1, RT pref, RT (&acc)[DIM + 2]) {
   constexpr int n = N + 1, h = n / 2;
   constexpr int NN = Shape<DIM, N>::NN;
   static_assert(n % 2 == 0, "packed half rounds need an even number of nodes per line");
@@ -319,8 +328,10 @@ __device__ __forceinline__ void volume_xy_half(const L& s, double* __restrict__ 
     a.v[1] = dy ? me.v[0] : me.v[1];
     q.v[0] = dy ? q1 : q0;
     q.v[1] = dy ? q0 : q1;
+    const RT ha[3] = {dy ? hme[1] : hme[0], dy ? hme[0] : hme[1], hme[2]};
     RT f[DIM + 2];
-    if constexpr (sizeof(RT) == 4) ec_flux_pp<DIM, 0>(a, q, inv_gm1, pref, f);
+    if constexpr (sizeof(RT) == 4) ec_flux_pp<DIM, 0>(a, ha, q, inv_gm1, pref, f);
+    else if constexpr (StagedHalfV<VOL>::value) ec_flux_h<DIM, 0, RT>(a, ha, q, inv_gm1, f);
     else ec_flux<DIM, 0, RT>(a, q, inv_gm1, f);
     const RT f1 = f[1], f2 = f[2];
     f[1] = dy ? f2 : f1;
@@ -802,7 +813,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
       if constexpr (CONS) s.c[li] = qd.c;
       s.rho[li] = (RT)qd.rho;
 #pragma unroll
-      for (int k = 0; k < DIM; ++k) s.v[k][li] = (RT)qd.v[k];
+      for (int k = 0; k < DIM; ++k) s.v[k][li] = (RT)(StagedHalfV<VOL>::value ? 0.5 * qd.v[k] : qd.v[k]);
       s.p[li] = (RT)(qd.p - pref);
       s.beta[li] = (RT)qd.beta;
       if constexpr (CONS) {
@@ -850,6 +861,9 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     me.rho = (RT)qd.rho;
 #pragma unroll
     for (int k = 0; k < 3; ++k) me.v[k] = (RT)qd.v[k];
+    RT hme[3];   // this node's velocity halved (the staged form of the EC volume)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) hme[k] = (RT)(0.5 * qd.v[k]);
     me.p = (RT)(qd.p - pref);
     me.beta = (RT)qd.beta;
     const RT inv_gm1 = (RT)(1.0 / (g.gamma - 1.0));
@@ -861,12 +875,12 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     for (int v = 0; v < NV; ++v) acc[v] = SEED ? (RT)R[v] : RT(0);
     // even n with the EC flux: the x and y half rounds run as one packed round
     constexpr bool PACK = (N % 2 == 1) && (VOL == VOL_EC || VOL == VOL_SHOCKCAP);
-    volume_dir<DIM, N, 0, VOL, RT, !PACK>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, (RT)pref, acc);
-    volume_dir<DIM, N, 1, VOL, RT, !PACK>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, (RT)pref, acc);
+    volume_dir<DIM, N, 0, VOL, RT, !PACK>(s, x, active, base, node, me, hme, um, sT + TAB_S, inv_gm1, (RT)pref, acc);
+    volume_dir<DIM, N, 1, VOL, RT, !PACK>(s, x, active, base, node, me, hme, um, sT + TAB_S, inv_gm1, (RT)pref, acc);
     if constexpr (PACK)
-      volume_xy_half<DIM, N, RT>(s, x, active, base, node, me, sT + TAB_S, inv_gm1, (RT)pref, acc);
+      volume_xy_half<DIM, N, VOL, RT>(s, x, active, base, node, me, hme, sT + TAB_S, inv_gm1, (RT)pref, acc);
     if constexpr (DIM == 3)
-      volume_dir<DIM, N, 2, VOL, RT, true>(s, x, active, base, node, me, um, sT + TAB_S, inv_gm1, (RT)pref, acc);
+      volume_dir<DIM, N, 2, VOL, RT, true>(s, x, active, base, node, me, hme, um, sT + TAB_S, inv_gm1, (RT)pref, acc);
     elem_sync<DIM, N>();   // every partner share has landed
     if (active) {
 #pragma unroll
