@@ -688,8 +688,10 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
     if (st != DGX_OK) return st;
     for (; s + 2 <= nsteps; s += 2) HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
   }
-  for (const int s0 = s; s < nsteps; ++s) {
-    dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, s + 1 < nsteps, s == s0);
+  for (; s < nsteps; ++s) {
+    // a fresh indicator at every even step, where each replayed pair starts: both paths take
+    // the same steps with the same numbers
+    dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, s + 1 < nsteps, s % 2 == 0);
     if (st != DGX_OK) return st;
   }
   if (cur != 0) {
