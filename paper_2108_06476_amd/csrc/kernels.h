@@ -177,14 +177,15 @@ __device__ __forceinline__ void face_flux(int surf, const double (&uL)[DIM + 2],
 // --------------------------------------------------------------------------------------
 // One stage of the right-hand side, one thread per node, Shape::NE elements per block
 // (element-tiled, staged in LDS):
-//   surface: every element evaluates the numerical flux on its 2*dim faces (the face nodes
-//            are spread over all threads of the block; each interface is evaluated by both
-//            of its elements from the same two states, so both get the same value), and
-//            lifts it to its boundary nodes:  +(2/h_d)/w_0 F* at i_d = 0, -(2/h_d)/w_N F* at i_d = N;
+//   surface: the thread of every face node evaluates the numerical flux with the neighbour's
+//            node across the face (each interface is evaluated by both of its elements from
+//            the same two states, so both get the same value) and lifts it to its node:
+//            +(2/h_d)/w_0 F* at i_d = 0, -(2/h_d)/w_N F* at i_d = N;
 //   volume:  -(2/h_d) sum_{m != i_d} S_{i_d m} f#(u, u_m), each pair evaluated once;
 //   shock capturing: R_vol = (1 - alpha) R_DG + alpha R_FV (alpha = 0 skips the FV part);
-//   epilogue: RHS: du = R;  RK: k = A k + dt R, u_out = u_in + B k, and optionally the
-//            per-block maximum wave speed of u_out for the next time step.
+//   epilogue: RHS: du = R;  RK: k = A k + dt R (not stored in a step's last stage),
+//            u_out = u_in + B k, optionally the per-element wave speeds of u_out for the
+//            next time step and (shock capturing) the raw indicator of u_out.
 // u_in is only read and u_out only written (they must differ in RK mode: neighbours read
 // u_in); k is read and written by the owning thread.
 // --------------------------------------------------------------------------------------
