@@ -39,6 +39,59 @@ def test_invalid_config_rejected_on_host(field, value):
     assert st == 1 and not h.value
 
 
+@pytest.mark.parametrize("case", ["no cells", "negative cells", "empty extent", "inverted extent",
+                                  "NaN gamma", "2D with cells in z", "alpha_max > 1",
+                                  "alpha_min >= 1/2", "FV flux EC"])
+def test_degenerate_grids_and_parameters_rejected(case):
+    """Empty grids, zero-width or inverted cells and out-of-range shock-capturing parameters are
+    rejected before any device call (DGX_EINVAL)."""
+    L = dgx.lib()
+    dim, cells, xmin, xmax = 3, [2, 2, 2], [0.0, 0.0, 0.0], [1.0, 1.0, 1.0]
+    extra = {}
+    if case == "no cells":
+        cells[1] = 0
+    elif case == "negative cells":
+        cells[2] = -3
+    elif case == "empty extent":
+        xmax[0] = xmin[0]
+    elif case == "inverted extent":
+        xmax[1] = -1.0
+    elif case == "NaN gamma":
+        extra["gamma"] = float("nan")
+    elif case == "2D with cells in z":
+        dim = 2
+    elif case == "alpha_max > 1":
+        extra.update(volume="shockcap_hg", alpha_max=1.5)
+    elif case == "alpha_min >= 1/2":
+        extra.update(volume="shockcap_hg", alpha_min=0.5)
+    elif case == "FV flux EC":
+        extra.update(volume="shockcap_hg", fv_flux="llf")
+    cfg = dgx.make_config(dim, 3, cells, xmin, xmax, **extra)
+    if case == "2D with cells in z":
+        cfg.cells[2] = 2
+    if case == "FV flux EC":
+        cfg.fv_flux = dgx.SURFACE["ec"]
+    h = C.c_void_p()
+    assert L.dgx_create(C.byref(cfg), None, C.byref(h)) == 1 and not h.value
+
+
+def test_curved_and_mhd_parameters_rejected():
+    L = dgx.lib()
+    h = C.c_void_p()
+    ok = dict(polydeg=3, cells=2, warp=0.1, gamma=1.4, volume=dgx.VOLUME["ec"],
+              surface=dgx.SURFACE["llf"], source=0)
+    for field, bad in [("cells", 0), ("warp", 0.5), ("warp", -0.1), ("polydeg", 0), ("gamma", 1.0),
+                       ("surface", 9), ("source", 7)]:
+        cv = dgx.CurvConfig(**dict(ok, **{field: bad}))
+        assert L.dgx_create_curved(C.byref(cv), None, C.byref(h)) == 1, (field, bad)
+    okm = dict(polydeg=3, cells=2, gamma=5.0 / 3.0, surface=dgx.SURFACE["hll"],
+               volume=dgx.VOLUME["weak"])
+    for field, bad in [("cells", 0), ("gamma", 0.9), ("volume", dgx.VOLUME["central"]),
+                       ("polydeg", -1)]:
+        mc = dgx.MhdConfig(**dict(okm, **{field: bad}))
+        assert L.dgx_create_mhd(C.byref(mc), None, C.byref(h)) == 1, (field, bad)
+
+
 def test_unsupported_config_reported():
     L = dgx.lib()
     h = C.c_void_p()
