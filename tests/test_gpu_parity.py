@@ -277,3 +277,24 @@ def test_pointer_validation():
     assert "device" in L.dgx_last_error(s._h).decode()
     with pytest.raises(ValueError):
         s.rhs(u, torch.empty(10, dtype=torch.float64, device="cuda"))
+
+
+def test_step_counts_zero_and_negative():
+    """nsteps = 0 changes neither the state nor t; a negative count or a step rule with
+    neither cfl nor dt is rejected before anything is enqueued."""
+    cfg = _cfg(3, 3, (3, 2, 2), "ec", "llf")
+    s = dgx.Solver(**cfg)
+    u = inputs.tgv(s.node_coords()).contiguous()
+    u0 = u.clone()
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.step(u, 0, cfl=0.5, t=t)
+    torch.cuda.synchronize()
+    assert torch.equal(u, u0) and float(t.item()) == 0.0
+    with pytest.raises(dgx.DgxError):
+        s.step(u, -1, cfl=0.5)
+    with pytest.raises(dgx.DgxError):
+        s.step(u, 1, cfl=0.0, dt_fixed=0.0)
+    assert torch.equal(u, u0)
+    s.step(u, 1, cfl=0.5, t=t)                      # the handle still works
+    torch.cuda.synchronize()
+    assert s.check() == 0 and float(t.item()) > 0.0
