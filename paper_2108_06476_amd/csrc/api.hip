@@ -447,6 +447,9 @@ dgx_status create_impl(const dgx_config& c, const dgx_curv_config* cv, void* hip
     delete h;
     return DGX_EINVAL;
   }
+  // curvilinear volume rounds contract with the sum of the pair's metric vectors: -S/2
+  if (cv)
+    for (int i = TAB_S; i < TAB_S + 3 * TMAX * TMAX; ++i) T[i] *= 0.5;
 
   const int64_t nblk = (h->E + L->ne - 1) / L->ne;
   h->npart = h->E;   // wave-speed partials: one per element

@@ -38,12 +38,16 @@ __device__ __forceinline__ void ja_of(const L& s, int i, int li, double (&a)[3])
 }
 
 // Unique-pair rounds along reference direction D (as volume_dir) with the two-point flux
-// contracted with the averaged metric vector of the pair.
+// contracted with the averaged metric vector of the pair.  Both fluxes are linear in that
+// vector, so the rounds contract with the sum of the two nodes' vectors and the handle's
+// table holds -S/2 (exact scalings: the same values).  The EC form reads the partner's
+// velocity halved (hme: this node's halves).
 template <int N, int D, int VOL, typename L>
 __device__ __forceinline__ void volume_dir_curv(const L& s, double* __restrict__ x, bool on,
                                                 int base, int node, const Prim<double>& me,
-                                                const double (&ume)[5], const double* sS,
-                                                double inv_gm1, double (&acc)[5]) {
+                                                const double (&hme)[3], const double (&ume)[5],
+                                                const double* sS, double inv_gm1,
+                                                double (&acc)[5]) {
   constexpr int n = N + 1, st = Stride<D, n>::value;
   constexpr int NN = Shape<3, N>::NN;
   constexpr int FULL = (n - 1) / 2;
@@ -68,14 +72,14 @@ __device__ __forceinline__ void volume_dir_curv(const L& s, double* __restrict__
       double ap[3], ab[3], f[5];
       ja_of(s, D, pn, ap);
 #pragma unroll
-      for (int k = 0; k < 3; ++k) ab[k] = 0.5 * (am[k] + ap[k]);
+      for (int k = 0; k < 3; ++k) ab[k] = am[k] + ap[k];
       if constexpr (VOL == VOL_CENTRAL) {
         double uq[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) uq[v] = s.u[v][pn];
         central_flux_vec(ume, me, uq, q, ab, f);
       } else {
-        ec_flux_vec(me, q, ab, inv_gm1, f);
+        ec_flux_vec_h(me, hme, q, ab, inv_gm1, f);
       }
       const double cme = sS[(D * TMAX + id) * TMAX + m];
       const double cpa = sS[(D * TMAX + m) * TMAX + id];
@@ -168,7 +172,7 @@ __device__ __forceinline__ void stage_tile_curv(typename CurvLdsOf<N, VOL>::type
     if (!cons_to_prim<3>(um, g.gamma, qd)) *g.flag = 1;
     s.rho[li] = qd.rho;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) s.v[k][li] = qd.v[k];
+    for (int k = 0; k < 3; ++k) s.v[k][li] = VOL == VOL_CENTRAL ? qd.v[k] : 0.5 * qd.v[k];
     s.p[li] = qd.p;
     s.beta[li] = qd.beta;
     if constexpr (VOL == VOL_CENTRAL) {
@@ -202,9 +206,10 @@ __device__ __forceinline__ void stage_tile_curv(typename CurvLdsOf<N, VOL>::type
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = R[v];
-    volume_dir_curv<N, 0, VOL>(s, x, active, base, node, qd, um, sT + TAB_S, inv_gm1, acc);
-    volume_dir_curv<N, 1, VOL>(s, x, active, base, node, qd, um, sT + TAB_S, inv_gm1, acc);
-    volume_dir_curv<N, 2, VOL>(s, x, active, base, node, qd, um, sT + TAB_S, inv_gm1, acc);
+    const double hme[3] = {0.5 * qd.v[0], 0.5 * qd.v[1], 0.5 * qd.v[2]};
+    volume_dir_curv<N, 0, VOL>(s, x, active, base, node, qd, hme, um, sT + TAB_S, inv_gm1, acc);
+    volume_dir_curv<N, 1, VOL>(s, x, active, base, node, qd, hme, um, sT + TAB_S, inv_gm1, acc);
+    volume_dir_curv<N, 2, VOL>(s, x, active, base, node, qd, hme, um, sT + TAB_S, inv_gm1, acc);
     elem_sync<3, N>();
     if (active) {
 #pragma unroll

@@ -323,6 +323,27 @@ __device__ __forceinline__ void ec_flux_vec(const Prim<double>& L, const Prim<do
   f[4] = frho * (ibeta * inv_gm1 + 0.5 * vLvR) + 0.5 * (L.p * vRa + R.p * vLa);
 }
 
+// ec_flux_vec with the partner's velocities stored halved (R.v = v_R/2), the node's own
+// halves hL beside its full L.v (as ec_flux_h), returning the flux contracted with a.
+__device__ __forceinline__ void ec_flux_vec_h(const Prim<double>& L, const double (&hL)[3],
+                                              const Prim<double>& R, const double (&a)[3],
+                                              double inv_gm1, double (&f)[5]) {
+  const double rho_ln = ln_mean(L.rho, R.rho);
+  const double ibeta = inv_ln_mean(L.beta, R.beta);
+  double vs[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) vs[k] = hL[k] + R.v[k];
+  const double vv = L.v[0] * R.v[0] + L.v[1] * R.v[1] + L.v[2] * R.v[2];   // v_L.v_R/2
+  const double frho = rho_ln * (vs[0] * a[0] + vs[1] * a[1] + vs[2] * a[2]);
+  const double pavg = 0.5 * (L.p + R.p);
+  f[0] = frho;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) f[1 + k] = frho * vs[k] + pavg * a[k];
+  const double hRa = R.v[0] * a[0] + R.v[1] * a[1] + R.v[2] * a[2];
+  const double hLa = hL[0] * a[0] + hL[1] * a[1] + hL[2] * a[2];
+  f[4] = frho * (ibeta * inv_gm1 + vv) + (L.p * hRa + R.p * hLa);
+}
+
 // Central two-point flux contracted with a: (f_a(u_L) + f_a(u_R))/2.
 __device__ __forceinline__ void central_flux_vec(const double (&uL)[5], const Prim<double>& L,
                                                  const double (&uR)[5], const Prim<double>& R,
