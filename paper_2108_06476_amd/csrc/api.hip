@@ -484,6 +484,7 @@ dgx_status create_impl(const dgx_config& c, const dgx_curv_config* cv, void* hip
   h->g.E = h->E;
   for (int d = 0; d < 3; ++d) h->g.K[d] = d < c.dim ? c.cells[d] : 1;
   h->g.gamma = c.gamma;
+  h->g.inv_gm1 = 1.0 / (c.gamma - 1.0);
   h->g.tab = h->tab;
   h->g.flag = h->flag;
   if (cv) {

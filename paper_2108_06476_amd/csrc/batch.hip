@@ -237,6 +237,7 @@ dgx_status dgx_batch_create(const dgx_config* cfgs, int32_t nruns, void* hip_str
     d.N = c.polydeg;
     d.surf = c.surface;
     d.gamma = c.gamma;
+    d.inv_gm1 = 1.0 / (c.gamma - 1.0);
     d.flag = b->flag_d;
     d.u = d.du = d.t = nullptr;
     b->nodes.push_back((int64_t)d.E * n * n * n);

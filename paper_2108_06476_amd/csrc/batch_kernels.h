@@ -20,7 +20,7 @@ struct RunDesc {
   double* speed;        // per-element wave-speed partials [E]
   const double* tab;    // operator tables
   int* flag;            // non-physical-state flag (shared by the batch)
-  double gamma;
+  double gamma, inv_gm1;   // inv_gm1 = 1/(gamma - 1)
   int E, K[3], N, surf;
 };
 

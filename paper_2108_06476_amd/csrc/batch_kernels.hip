@@ -42,6 +42,7 @@ __device__ __forceinline__ Geom run_geom(const RunDesc& d) {
   g.K[1] = d.K[1];
   g.K[2] = d.K[2];
   g.gamma = d.gamma;
+  g.inv_gm1 = d.inv_gm1;
   g.tab = d.tab;
   g.flag = d.flag;
   return g;

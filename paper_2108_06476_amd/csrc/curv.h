@@ -202,7 +202,7 @@ __device__ __forceinline__ void stage_tile_curv(typename CurvLdsOf<N, VOL>::type
   }
   if constexpr (VOL != VOL_NONE) {
     double* x = reinterpret_cast<double*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);
-    const double inv_gm1 = 1.0 / (g.gamma - 1.0);
+    const double inv_gm1 = g.inv_gm1;
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = R[v];

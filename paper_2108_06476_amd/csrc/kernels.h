@@ -52,6 +52,7 @@ struct Geom {
   double gamma;
   const double* tab;
   int* flag;   // set to 1 when a non-physical state is met
+  double inv_gm1 = 0.0;          // 1/(gamma - 1), formed once on the host
   // curvilinear elements (nullptr: Cartesian)
   const double* ja = nullptr;    // (J a^i)_n, [3 (i)][3 (n)][E][NN]
   const double* jac = nullptr;   // J, [E][NN]
@@ -445,7 +446,7 @@ __device__ __forceinline__ void surface_dir(const Geom& g, int surf, int node,
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v] = 0.5 * (fo[v] + fn[v]) - hl * (un[v] - um[v]);
   } else if (surf == SURF_EC) {
-    ec_flux_sym<DIM, D>(qm, qn, 1.0 / (g.gamma - 1.0), F);
+    ec_flux_sym<DIM, D>(qm, qn, g.inv_gm1, F);
   } else {
     double uL[NV], uR[NV];
     Prim<double> qL, qR;
@@ -867,7 +868,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
     for (int k = 0; k < 3; ++k) hme[k] = (RT)(0.5 * qd.v[k]);
     me.p = (RT)(qd.p - pref);
     me.beta = (RT)qd.beta;
-    const RT inv_gm1 = (RT)(1.0 / (g.gamma - 1.0));
+    const RT inv_gm1 = (RT)g.inv_gm1;
     // float64 without blending: the surface terms seed the volume accumulator (fewer live
     // registers through the pair rounds)
     constexpr bool SEED = (VOL != VOL_SHOCKCAP) && sizeof(RT) == 8;

@@ -349,7 +349,7 @@ __device__ __forceinline__ void mhd_ec_face(const Geom& g, const StageArgs& a, c
   if (!mhd_prim(un, g.gamma, qn)) *g.flag = 1;
   if (a.surf == SURF_EC) {
     const MhdNode nn = mhd_node(qn);
-    mhd_ec_flux<D>(plus ? me : nn, plus ? nn : me, 1.0 / (g.gamma - 1.0), F);
+    mhd_ec_flux<D>(plus ? me : nn, plus ? nn : me, g.inv_gm1, F);
   } else {
 #pragma unroll
     for (int v = 0; v < 8; ++v) {
@@ -433,7 +433,7 @@ __global__ __launch_bounds__((Shape<3, N>::THREADS), 3) void k_stage_mhd_ec(Stag
     mhd_ec_face<N, 1>(g, a, sT, e, ec, node, um, qm, me, phi, R);
     mhd_ec_face<N, 2>(g, a, sT, e, ec, node, um, qm, me, phi, R);
   }
-  const double inv_gm1 = 1.0 / (g.gamma - 1.0);
+  const double inv_gm1 = g.inv_gm1;
   mhd_ec_dir<N, 0>(s, x, active, base, node, me, phi, sT + TAB_S, inv_gm1, R);
   mhd_ec_dir<N, 1>(s, x, active, base, node, me, phi, sT + TAB_S, inv_gm1, R);
   mhd_ec_dir<N, 2>(s, x, active, base, node, me, phi, sT + TAB_S, inv_gm1, R);
