@@ -24,6 +24,9 @@ sys.path.insert(0, ROOT)
 METRIC = "DOF-RHS evals/sec (PID) 3D Euler N=3, FP64 vs mixed vs batched, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
 FP64_VALU_PEAK_TFLOPS = 78.6   # 256 CUs x 2.4 GHz x 128 FP64 flops per clock
+# vector-instruction issue: 1024 SIMDs x 2.4 GHz, one 64-lane instruction per 4 clocks
+# (16 lanes a clock; float64 FMAs and 32-bit operations alike)
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -203,6 +206,12 @@ def main():
                 "fp64_flops_per_launch": pmc["fp64_flops_per_launch"],
                 "valu_insts_per_wave": pmc.get("valu_insts_per_wave"),
                 "fp64_share_of_valu_insts": pmc.get("fp64_share_of_valu_insts")}
+        cpl = pmc.get("counters_per_launch", {})
+        if cpl.get("SQ_INSTS_VALU"):
+            # all vector instructions (float64, address, select, move) against the issue peak
+            rate = cpl["SQ_INSTS_VALU"] / (avg_ms * 1e-3)
+            valu["issue"] = {"achieved": round(rate / 1e9, 1), "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+                             "unit": "G wave-instructions/s", "frac": round(rate / VALU_ISSUE_PEAK, 4)}
     _log(f"step: {secs / args.steps * 1e3:.3f} ms/step, {value:.4e} DOF-RHS/s; "
          f"{kname} avg {avg_ms * 1e3:.1f} us")
 
