@@ -65,20 +65,13 @@ __device__ __forceinline__ double artanh_over_z(double z2) {
 // z^2 = 0.1 (states within a factor 1.9) the 16-term series of artanh(z)/z replaces the
 // logarithm and its two divisions (MID; a kernel that never meets such jumps and is short of
 // registers leaves it out); beyond it the logarithm.
-// 1 + y (c1 + c2 y + c3 y^2) for y = z^2 < 1e-4.  The constants enter as multiplicands or a
-// plain addend (scalar-register operands), never as the addend of a fused multiply-add,
-// which would copy each into vector registers first; the bracket's rounding is scaled by y.
-__device__ __forceinline__ double series3(double y, double c1, double c2, double c3) {
-  const double q = fma(c3, y * y, c2 * y) + c1;
-  return fma(y, q, 1.0);
-}
-
 template <bool MID = true>
 __device__ __forceinline__ double ln_mean(double a, double b) {
   const double s = a + b, d = b - a;
   const double r = rcp_nr1(s);   // only z is formed from it
   const double z = d * r, z2 = z * z;
-  if (z2 < 1.0e-4) return 0.5 * s * series3(z2, -1.0 / 3.0, -4.0 / 45.0, -44.0 / 945.0);
+  if (z2 < 1.0e-4)
+    return 0.5 * s * (1.0 + z2 * (-1.0 / 3.0 + z2 * (-4.0 / 45.0 + z2 * (-44.0 / 945.0))));
   if (MID && z2 < 0.1) return 0.5 * s * rcp_nr(artanh_over_z(z2));
   const double hi = fmax(a, b), lo = fmin(a, b);   // symmetric in (a, b), bit for bit
   return (hi - lo) / log(hi / lo);
@@ -89,7 +82,8 @@ __device__ __forceinline__ double inv_ln_mean(double a, double b) {
   const double s = a + b, d = b - a;
   const double r = rcp_nr(s);
   const double z = d * r, z2 = z * z;
-  if (z2 < 1.0e-4) return 2.0 * r * series3(z2, 1.0 / 3.0, 1.0 / 5.0, 1.0 / 7.0);
+  if (z2 < 1.0e-4)
+    return 2.0 * r * (1.0 + z2 * (1.0 / 3.0 + z2 * (1.0 / 5.0 + z2 * (1.0 / 7.0))));
   if (MID && z2 < 0.1) return 2.0 * r * artanh_over_z(z2);
   const double hi = fmax(a, b), lo = fmin(a, b);
   return log(hi / lo) / (hi - lo);
