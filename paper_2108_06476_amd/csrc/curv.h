@@ -42,7 +42,7 @@ __device__ __forceinline__ void ja_of(const L& s, int i, int li, double (&a)[3])
 // vector, so the rounds contract with the sum of the two nodes' vectors and the handle's
 // table holds -S/2 (exact scalings: the same values).  The EC form reads the partner's
 // velocity halved (hme: this node's halves).
-template <int N, int D, int VOL, typename L>
+template <int N, int D, int VOL, bool HALF, typename L>
 __device__ __forceinline__ void volume_dir_curv(const L& s, double* __restrict__ x, bool on,
                                                 int base, int node, const Prim<double>& me,
                                                 const double (&hme)[3], const double (&ume)[5],
@@ -51,7 +51,7 @@ __device__ __forceinline__ void volume_dir_curv(const L& s, double* __restrict__
   constexpr int n = N + 1, st = Stride<D, n>::value;
   constexpr int NN = Shape<3, N>::NN;
   constexpr int FULL = (n - 1) / 2;
-  constexpr int ROUNDS = FULL + (n % 2 == 0 ? 1 : 0);
+  constexpr int ROUNDS = FULL + (HALF && n % 2 == 0 ? 1 : 0);
   const int id = (node / st) % n;
   const int nb = base + node - id * st;
   double am[3];
@@ -91,6 +91,56 @@ __device__ __forceinline__ void volume_dir_curv(const L& s, double* __restrict__
     }
     if constexpr (!WaveElem<3, N>::value) __syncthreads();
   }
+}
+
+// The half rounds of the first two reference directions in one full round (even n): the
+// pairing of the Cartesian kernels' packed round (a node whose x and y indices lie on the
+// same side of n/2 takes its x pair, the others their y pair).  The contracted fluxes take
+// the direction only through the metric vectors and the table row, so no components move.
+template <int N, int VOL, typename L>
+__device__ __forceinline__ void volume_xy_half_curv(const L& s, double* __restrict__ x, bool on,
+                                                    int base, int node, const Prim<double>& me,
+                                                    const double (&hme)[3],
+                                                    const double (&ume)[5], const double* sS,
+                                                    double inv_gm1, double (&acc)[5]) {
+  constexpr int n = N + 1, h = n / 2;
+  constexpr int NN = Shape<3, N>::NN;
+  static_assert(n % 2 == 0, "packed half rounds need an even number of nodes per line");
+  const int ix = node % n, iy = (node / n) % n;
+  const bool dy = (ix < h) != (iy < h);
+  const int D = dy ? 1 : 0;
+  const int id = dy ? iy : ix;
+  const int m = id < h ? id + h : id - h;
+  const int pn = base + node + (m - id) * (dy ? n : 1);
+  if (on) {
+    Prim<double> q;
+    q.rho = s.rho[pn];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) q.v[k] = s.v[k][pn];
+    q.p = s.p[pn];
+    q.beta = s.beta[pn];
+    double am[3], ap[3], ab[3], f[5];
+    ja_of(s, D, base + node, am);
+    ja_of(s, D, pn, ap);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) ab[k] = am[k] + ap[k];
+    if constexpr (VOL == VOL_CENTRAL) {
+      double uq[5];
+#pragma unroll
+      for (int v = 0; v < 5; ++v) uq[v] = s.u[v][pn];
+      central_flux_vec(ume, me, uq, q, ab, f);
+    } else {
+      ec_flux_vec_h(me, hme, q, ab, inv_gm1, f);
+    }
+    const double cme = sS[(D * TMAX + id) * TMAX + m];
+    const double cpa = sS[(D * TMAX + m) * TMAX + id];
+#pragma unroll
+    for (int v = 0; v < 5; ++v) {
+      acc[v] += cme * f[v];
+      lds_add(&x[v * NN + pn - base], cpa * f[v]);
+    }
+  }
+  if constexpr (!WaveElem<3, N>::value) __syncthreads();
 }
 
 // Face term along reference direction D for a boundary node: the interface flux through the
@@ -207,9 +257,13 @@ __device__ __forceinline__ void stage_tile_curv(typename CurvLdsOf<N, VOL>::type
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = R[v];
     const double hme[3] = {0.5 * qd.v[0], 0.5 * qd.v[1], 0.5 * qd.v[2]};
-    volume_dir_curv<N, 0, VOL>(s, x, active, base, node, qd, hme, um, sT + TAB_S, inv_gm1, acc);
-    volume_dir_curv<N, 1, VOL>(s, x, active, base, node, qd, hme, um, sT + TAB_S, inv_gm1, acc);
-    volume_dir_curv<N, 2, VOL>(s, x, active, base, node, qd, hme, um, sT + TAB_S, inv_gm1, acc);
+    // even n: the x and y half rounds run as one packed round
+    constexpr bool PACK = N % 2 == 1;
+    volume_dir_curv<N, 0, VOL, !PACK>(s, x, active, base, node, qd, hme, um, sT + TAB_S, inv_gm1, acc);
+    volume_dir_curv<N, 1, VOL, !PACK>(s, x, active, base, node, qd, hme, um, sT + TAB_S, inv_gm1, acc);
+    if constexpr (PACK)
+      volume_xy_half_curv<N, VOL>(s, x, active, base, node, qd, hme, um, sT + TAB_S, inv_gm1, acc);
+    volume_dir_curv<N, 2, VOL, true>(s, x, active, base, node, qd, hme, um, sT + TAB_S, inv_gm1, acc);
     elem_sync<3, N>();
     if (active) {
 #pragma unroll
