@@ -295,8 +295,8 @@ dgx_status enqueue_rhs(dgx_handle h, const double* u, double* du, const double* 
 // One RK step on h->stream: dt (adaptive: from the partials in h->partial), then the five
 // stages; emit: the last stage writes the next step's partials.  cur: which of buf holds
 // the state (toggled by every stage).  Shock capturing: every stage writes the raw
-// indicator of its output state, so a stage only smooths it, except the first stage of a
-// step with fresh set (the first of a call or of a captured graph), which computes it.
+// indicator of its output state and smooths its input's itself; the first stage of a step
+// with fresh set (the first of a call or of a captured graph) has it computed first.
 dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double cfl,
                         double dt_fixed, double* t, bool emit, bool fresh) {
   const bool adaptive = cfl > 0.0;
@@ -308,21 +308,22 @@ dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double 
     hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, h->stream, dt_fixed, h->dt, t, t0);
   }
   HIPCHK(h, hipGetLastError());
+  // shock capturing: the raw indicator alternates between two buffers, each stage smoothing
+  // its input's and emitting its output's; a fresh step starts from k_indicator's
+  const bool shock = h->cfg.volume == DGX_VOL_SHOCKCAP_HG && !h->curved && !h->mhd;
+  double* const araw[2] = {h->alpha_raw, h->alpha};
   for (int st = 0; st < 5; ++st) {
     const double* uin = buf[cur];
-    const double* alpha = nullptr;
-    if (h->cfg.volume == DGX_VOL_SHOCKCAP_HG && !h->curved && !h->mhd) {
-      if (st == 0 && fresh) {
-        dgx_status r = enqueue_indicator(h, uin, h->alpha, h->alpha_raw, nullptr);
-        if (r != DGX_OK) return r;
-      } else {
-        HIPCHK(h, h->L->smooth(h->stream, h->alpha_raw, h->alpha, h->g, h->cfg.alpha_smooth));
-      }
-      alpha = h->alpha;
+    const int j = (fresh ? 0 : 5) + st;   // stages since the indicator ran on a state
+    if (shock && st == 0 && fresh) {
+      HIPCHK(h, h->L->indicator(h->stream, uin, araw[0], nullptr, h->g, h->cfg.alpha_min,
+                                h->cfg.alpha_max));
     }
-    StageArgs a = stage_args(h, uin, alpha);
-    if (alpha) {
-      a.alpha_next = h->alpha_raw;
+    StageArgs a = stage_args(h, uin, nullptr);
+    if (shock) {
+      a.alpha_raw_in = araw[j % 2];
+      a.alpha_smooth = h->cfg.alpha_smooth;
+      a.alpha_next = araw[(j + 1) % 2];
       indicator_constants(h->N, a.ind_thr, a.ind_sharp);
       a.ind_amin = h->cfg.alpha_min;
       a.ind_amax = h->cfg.alpha_max;
@@ -334,8 +335,8 @@ dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double 
     a.t0 = t0;
     a.cs = CK_C[st];
     a.kw = st < 4;
-    // stages of one step run back to back unless indicator kernels sit between them
-    HIPCHK(h, launch_stage(h, a, EPI_RK, st == 4 || alpha != nullptr));
+    // the stages of one step run back to back (an indicator kernel only precedes stage 0)
+    HIPCHK(h, launch_stage(h, a, EPI_RK, st == 4));
     cur = 1 - cur;
   }
   return DGX_OK;

@@ -498,6 +498,10 @@ struct StageArgs {
   // its constants (threshold, sharpness, alpha_min, alpha_max)
   double* alpha_next = nullptr;
   double ind_thr = 0.0, ind_sharp = 0.0, ind_amin = 0.0, ind_amax = 0.0;
+  // shock capturing: the raw indicator of the stage's input (nullptr: alpha holds the
+  // smoothed factors); each element then smooths its own from it and its face neighbours'
+  const double* alpha_raw_in = nullptr;
+  int alpha_smooth = 0;
 };
 
 // Weak form: the physical fluxes f^d_v of every node, contracted along the lines.
@@ -776,9 +780,28 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   // of -(2/h_d) S (minus the lift factor at a face node, zero inside), cancels exactly
   // against p_ref in the lifted surface flux, which is removed there in float64 instead.
   double pref = 0.0;
+  double al_e = 0.0;   // shock capturing: the element's blending factor
   if (active) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) um[v] = (a.uin + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
+    if constexpr (VOL == VOL_SHOCKCAP) {
+      if (a.alpha_raw_in) {   // alpha_e = max(raw_e, raw of the face neighbours / 2)
+        const double* ar = a.alpha_raw_in;
+        double v = ar[e];
+        if (a.alpha_smooth) {
+          int ec[3];
+          elem_xyz(g, e, ec);
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            v = fmax(v, 0.5 * ar[elem_nb(g, e, ec, d, -1)]);
+            v = fmax(v, 0.5 * ar[elem_nb(g, e, ec, d, 1)]);
+          }
+        }
+        al_e = v;
+      } else {
+        al_e = a.alpha[e];
+      }
+    }
     if constexpr (sizeof(RT) == 4 && !WaveElem<DIM, N>::value) {
       double u0[NV];
 #pragma unroll
@@ -892,7 +915,7 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
       // blended subcell FV part: the partner-share slot x is free once every node has read
       // its shares and holds the shared subcell fluxes; a one-wave element skips it when its
       // alpha is zero, a block of other shapes when every alpha in it is zero
-      const double al = active ? a.alpha[e] : 0.0;
+      const double al = al_e;
       double fv[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) fv[v] = 0.0;
