@@ -161,8 +161,10 @@ struct dgx_solver {
   bool mhd = false;         // ideal MHD (dgx_create_mhd): 8 variables
   // two RK steps captured in a hipGraph (replayed by dgx_step), valid for one key
   hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;     // a step pair starting a call (shock capturing: fresh)
   hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph2 = nullptr;    // shock capturing: a step pair continuing one
+  hipGraphExec_t gexec2 = nullptr;
   const double* g_u = nullptr;
   const double* g_t = nullptr;
   double g_cfl = 0.0, g_dtf = 0.0;
@@ -296,9 +298,14 @@ dgx_status enqueue_rhs(dgx_handle h, const double* u, double* du, const double* 
 // stages; emit: the last stage writes the next step's partials.  cur: which of buf holds
 // the state (toggled by every stage).  Shock capturing: every stage writes the raw
 // indicator of its output state and smooths its input's itself; the first stage of a step
-// with fresh set (the first of a call or of a captured graph) has it computed first.
+// with fresh set (the first of a call) has it computed first.  j0: the parity of the
+// number of stages since then, which picks the buffer each stage reads.
+bool shock_steps(dgx_handle h) {
+  return h->cfg.volume == DGX_VOL_SHOCKCAP_HG && !h->curved && !h->mhd;
+}
+
 dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double cfl,
-                        double dt_fixed, double* t, bool emit, bool fresh) {
+                        double dt_fixed, double* t, bool emit, bool fresh, int j0) {
   const bool adaptive = cfl > 0.0;
   double* t0 = h->g.source ? h->t0 : nullptr;   // step start time for the stage times
   if (adaptive) {
@@ -310,11 +317,11 @@ dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double 
   HIPCHK(h, hipGetLastError());
   // shock capturing: the raw indicator alternates between two buffers, each stage smoothing
   // its input's and emitting its output's; a fresh step starts from k_indicator's
-  const bool shock = h->cfg.volume == DGX_VOL_SHOCKCAP_HG && !h->curved && !h->mhd;
+  const bool shock = shock_steps(h);
   double* const araw[2] = {h->alpha_raw, h->alpha};
   for (int st = 0; st < 5; ++st) {
     const double* uin = buf[cur];
-    const int j = (fresh ? 0 : 5) + st;   // stages since the indicator ran on a state
+    const int j = j0 + st;   // parity of the stages since the indicator ran on a state
     if (shock && st == 0 && fresh) {
       HIPCHK(h, h->L->indicator(h->stream, uin, araw[0], nullptr, h->g, h->cfg.alpha_min,
                                 h->cfg.alpha_max));
@@ -345,25 +352,27 @@ dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double 
 void drop_step_graph(dgx_handle h) {
   if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->gexec2) (void)hipGraphExecDestroy(h->gexec2);
+  if (h->graph2) (void)hipGraphDestroy(h->graph2);
   h->gexec = nullptr;
   h->graph = nullptr;
+  h->gexec2 = nullptr;
+  h->graph2 = nullptr;
   h->g_u = nullptr;
 }
 
-// Two RK steps (both emitting the next partials) captured on a private stream; the graph
-// is reused while the state pointer, t and the step rule stay the same.
-dgx_status ensure_step_graph(dgx_handle h, double* u, double cfl, double dt_fixed, double* t) {
-  if (h->gexec && h->g_u == u && h->g_t == t && h->g_cfl == cfl && h->g_dtf == dt_fixed)
-    return DGX_OK;
-  drop_step_graph(h);
+// One pair of RK steps (both emitting the next partials) captured on a private stream;
+// fresh: its first step starts a call.
+dgx_status capture_step_pair(dgx_handle h, double* u, double cfl, double dt_fixed, double* t,
+                             bool fresh, hipGraph_t& graph, hipGraphExec_t& exec) {
   if (!h->cap) HIPCHK(h, hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
   HIPCHK(h, hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
   hipStream_t user = h->stream;
   h->stream = h->cap;
   double* buf[2] = {u, h->u2};
   int cur = 0;
-  dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, true, true);
-  if (st == DGX_OK) st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, true, false);
+  dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, true, fresh, 0);
+  if (st == DGX_OK) st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, true, false, 1);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(h->cap, &g);
   h->stream = user;
@@ -371,8 +380,24 @@ dgx_status ensure_step_graph(dgx_handle h, double* u, double cfl, double dt_fixe
     if (g) (void)hipGraphDestroy(g);
     return st != DGX_OK ? st : fail(h, DGX_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
   }
-  h->graph = g;
-  HIPCHK(h, hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+  graph = g;
+  HIPCHK(h, hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+  return DGX_OK;
+}
+
+// The captured step pairs, reused while the state pointer, t and the step rule stay the
+// same: one that starts a call and, with shock capturing (whose first stage of a call runs
+// the indicator), one that continues it.
+dgx_status ensure_step_graph(dgx_handle h, double* u, double cfl, double dt_fixed, double* t) {
+  if (h->gexec && h->g_u == u && h->g_t == t && h->g_cfl == cfl && h->g_dtf == dt_fixed)
+    return DGX_OK;
+  drop_step_graph(h);
+  dgx_status st = capture_step_pair(h, u, cfl, dt_fixed, t, true, h->graph, h->gexec);
+  if (st != DGX_OK) return st;
+  if (shock_steps(h)) {
+    st = capture_step_pair(h, u, cfl, dt_fixed, t, false, h->graph2, h->gexec2);
+    if (st != DGX_OK) return st;
+  }
   h->g_u = u;
   h->g_t = t;
   h->g_cfl = cfl;
@@ -691,12 +716,13 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
     // pairs of steps from the captured graph (ten stages: the state is back in u)
     dgx_status st = ensure_step_graph(h, u, cfl, dt_fixed, t);
     if (st != DGX_OK) return st;
-    for (; s + 2 <= nsteps; s += 2) HIPCHK(h, hipGraphLaunch(h->gexec, h->stream));
+    for (; s + 2 <= nsteps; s += 2)
+      HIPCHK(h, hipGraphLaunch(s == 0 || !h->gexec2 ? h->gexec : h->gexec2, h->stream));
   }
   for (; s < nsteps; ++s) {
-    // a fresh indicator at every even step, where each replayed pair starts: both paths take
-    // the same steps with the same numbers
-    dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, s + 1 < nsteps, s % 2 == 0);
+    // the indicator only before the call's first stage: the replayed pairs and these steps
+    // run the same kernels on the same numbers
+    dgx_status st = enqueue_step(h, buf, cur, cfl, dt_fixed, t, s + 1 < nsteps, s == 0, s % 2);
     if (st != DGX_OK) return st;
   }
   if (cur != 0) {
