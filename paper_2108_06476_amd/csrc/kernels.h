@@ -221,11 +221,12 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// The EC volume stages the nodes' velocities halved (exact), which saves multiplications in
-// the pair flux (ec_flux_h); the blended FV and central forms read them whole.
+// The EC and blended volumes stage the nodes' velocities halved (exact), which saves
+// multiplications in the pair flux (ec_flux_h); the subcell FV fluxes double them back and
+// the central form reads them whole.
 template <int VOL>
 struct StagedHalfV {
-  static constexpr bool value = VOL == VOL_EC;
+  static constexpr bool value = VOL == VOL_EC || VOL == VOL_SHOCKCAP;
 };
 
 // Unique pairs along direction D.  In round r every node i pairs with i + r (mod n) and
@@ -373,7 +374,7 @@ __device__ __forceinline__ void fv_dir(const L& s, double* __restrict__ f, int f
     q.rho = s.rho[pn];
     q.v[0] = q.v[1] = q.v[2] = 0.0;
 #pragma unroll
-    for (int k = 0; k < DIM; ++k) q.v[k] = s.v[k][pn];
+    for (int k = 0; k < DIM; ++k) q.v[k] = 2.0 * s.v[k][pn];   // staged halved (blended volume)
     q.p = s.p[pn];
     q.beta = s.beta[pn];
     q.c = s.c[pn];
