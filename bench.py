@@ -194,24 +194,7 @@ def main():
                 "traffic": stored_traffic("k_stage_tgv32_fp64"),
                 "kernel": kname, "avg_ms": avg_ms, "launches": launches,
                 "alg_bytes_per_launch": alg_bytes}
-    # The same kernel against the FP64 vector peak: FP64 flops per launch from the committed
-    # counter summary (64 lanes x (ADD + MUL + TRANS + 2 FMA) FP64 VALU instructions, masked
-    # lanes included), over this run's live launch time; null once the sources changed.
-    pmc = stored_pmc("k_stage_tgv32_fp64")
-    valu = None
-    if pmc is not None and pmc.get("fp64_flops_per_launch"):
-        tf = pmc["fp64_flops_per_launch"] / (avg_ms * 1e-3) / 1e12
-        valu = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(tf / FP64_VALU_PEAK_TFLOPS, 4),
-                "fp64_flops_per_launch": pmc["fp64_flops_per_launch"],
-                "valu_insts_per_wave": pmc.get("valu_insts_per_wave"),
-                "fp64_share_of_valu_insts": pmc.get("fp64_share_of_valu_insts")}
-        cpl = pmc.get("counters_per_launch", {})
-        if cpl.get("SQ_INSTS_VALU"):
-            # all vector instructions (float64, address, select, move) against the issue peak
-            rate = cpl["SQ_INSTS_VALU"] / (avg_ms * 1e-3)
-            valu["issue"] = {"achieved": round(rate / 1e9, 1), "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
-                             "unit": "G wave-instructions/s", "frac": round(rate / VALU_ISSUE_PEAK, 4)}
+    valu = valu_object(stored_pmc("k_stage_tgv32_fp64"), avg_ms)
     _log(f"step: {secs / args.steps * 1e3:.3f} ms/step, {value:.4e} DOF-RHS/s; "
          f"{kname} avg {avg_ms * 1e3:.1f} us")
 
@@ -444,6 +427,28 @@ def kernel_source_hash():
             h.update(os.path.basename(f).encode())
             h.update(open(f, "rb").read())
     return h.hexdigest()
+
+
+def valu_object(pmc, avg_ms):
+    """The stage kernel against the FP64 vector peak: FP64 flops per launch from the committed
+    counter summary (64 lanes x (ADD + MUL + TRANS + 2 FMA) FP64 VALU instructions, masked
+    lanes included) over the live launch time avg_ms, and all its vector instructions against
+    the issue peak; None without a summary of the current sources."""
+    if pmc is None or not pmc.get("fp64_flops_per_launch"):
+        return None
+    tf = pmc["fp64_flops_per_launch"] / (avg_ms * 1e-3) / 1e12
+    valu = {"bound": "alu", "achieved": round(tf, 2), "peak": FP64_VALU_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(tf / FP64_VALU_PEAK_TFLOPS, 4),
+            "fp64_flops_per_launch": pmc["fp64_flops_per_launch"],
+            "valu_insts_per_wave": pmc.get("valu_insts_per_wave"),
+            "fp64_share_of_valu_insts": pmc.get("fp64_share_of_valu_insts")}
+    cpl = pmc.get("counters_per_launch", {})
+    if cpl.get("SQ_INSTS_VALU"):
+        # all vector instructions (float64, address, select, move) against the issue peak
+        rate = cpl["SQ_INSTS_VALU"] / (avg_ms * 1e-3)
+        valu["issue"] = {"achieved": round(rate / 1e9, 1), "peak": round(VALU_ISSUE_PEAK / 1e9, 1),
+                         "unit": "G wave-instructions/s", "frac": round(rate / VALU_ISSUE_PEAK, 4)}
+    return valu
 
 
 def stored_pmc(name):

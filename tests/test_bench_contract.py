@@ -47,3 +47,21 @@ def test_stored_counters_are_gated_by_the_source_hash(monkeypatch):
     monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 64)
     assert bench.stored_traffic("k_stage_tgv32_fp64") is None
     assert bench.stored_pmc("k_stage_tgv32_fp64") is None
+
+
+def test_valu_object_from_the_stored_counters():
+    """FP64 rate and vector-issue rate of the stage kernel from the committed counters: the
+    arithmetic by hand, and None without a summary."""
+    rec = json.load(open(os.path.join(ROOT, "profiles", "k_stage_tgv32_fp64_pmc.json")))
+    avg_ms = 0.075
+    v = bench.valu_object(rec, avg_ms)
+    flops = rec["fp64_flops_per_launch"]
+    assert abs(v["achieved"] - flops / 75e-6 / 1e12) < 0.01
+    assert v["peak"] == 78.6 and abs(v["frac"] - v["achieved"] / 78.6) < 1e-3
+    insts = rec["counters_per_launch"]["SQ_INSTS_VALU"]
+    # 1024 SIMDs x 2.4 GHz / 4 clocks per 64-lane instruction
+    assert v["issue"]["peak"] == 614.4
+    assert abs(v["issue"]["frac"] - insts / 75e-6 / 614.4e9) < 1e-3
+    # the counters hold 64 lanes per instruction: SQ_INSTS_VALU / SQ_WAVES is the per-wave count
+    assert abs(insts / rec["counters_per_launch"]["SQ_WAVES"] - rec["valu_insts_per_wave"]) < 0.1
+    assert bench.valu_object(None, avg_ms) is None
