@@ -1,14 +1,19 @@
 """Helpers of the GPU parity tests: device transfer and the flux-scale error norm.
 
 Parity norm per field v (float64):
-    err_v = max_n |R_gpu_v - R_orc_v| / ((2/h) max(max_{n,d} |f^d_v(u_n)|, lambda_max max_n |u_v,n|)),
-i.e. the difference relative to the scale of the terms that the right-hand side sums: the
-physical fluxes, and the dissipation terms lambda (u_R - u_L)/2 of the LLF/HLL interface and
-subcell fluxes (lambda_max = max |v_d| + c).  The second term matters where v = 0 makes
-the mass and energy fluxes vanish (a blast wave at rest).
+    err_v = max_n |R_gpu_v - R_orc_v| / ((2/h) max_{n,d} |f^d_v(u_n)|),
+the difference relative to the scale of the flux terms that the right-hand side sums.  Only
+for a field whose flux scale is exactly zero (a state at rest: the mass and energy fluxes of
+the blast-wave initial state vanish) the scale is lambda_max max_n |u_v,n| instead
+(lambda_max = max |v_d| + c): the terms that remain are then the dissipation terms
+lambda (u_R - u_L)/2 of the LLF/HLL interface and subcell fluxes.
 Two correct float64 evaluations that only differ in summation order, FMA contraction or an
 algebraically equivalent log-mean form differ at the 1e-15 level in this norm; the bar is
 1e-12.
+
+State norm after time steps: max_n |u_gpu_v - u_orc_v| / max_n |u_orc_v|, where the three
+momentum components share one denominator (the largest of the three: a component can start
+at zero), also bounded by 1e-12.
 """
 import numpy as np
 import torch
@@ -48,10 +53,26 @@ def dissipation_max(u, dim, gamma=1.4):
     return lam * np.abs(uu).max(axis=1)
 
 
+def err_scale(u, dim, h, gamma=1.4):
+    """(2/h) max_{n,d} |f^d_v| per field; (2/h) lambda_max max |u_v| where that is zero."""
+    fs = phys_flux_max(u, dim, gamma)
+    return (2.0 / h) * np.where(fs > 0.0, fs, dissipation_max(u, dim, gamma))
+
+
 def err_v(R_gpu, R_orc, u, dim, h, gamma=1.4):
-    scale = (2.0 / h) * np.maximum(phys_flux_max(u, dim, gamma), dissipation_max(u, dim, gamma))
     d = np.abs(np.asarray(R_gpu) - np.asarray(R_orc)).reshape(dim + 2, -1).max(axis=1)
-    return d / scale
+    return d / err_scale(u, dim, h, gamma)
+
+
+def state_err(u_gpu, u_orc, dim):
+    """Per-field state difference after steps: max |du_v| / max |u_v|, the momentum
+    components against the largest momentum magnitude."""
+    a = np.asarray(u_gpu).reshape(dim + 2, -1)
+    b = np.asarray(u_orc).reshape(dim + 2, -1)
+    d = np.abs(a - b).max(axis=1)
+    m = np.abs(b).max(axis=1)
+    m[1:1 + dim] = m[1:1 + dim].max()
+    return d / np.maximum(m, 1e-300)
 
 
 def rel_to_max(a, b):

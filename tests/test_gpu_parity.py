@@ -12,7 +12,7 @@ import torch
 import oracle
 from paper_2108_06476_amd import dgx, inputs
 
-from gpu_util import TOL_FP64, dev, err_v, host, rel_to_max
+from gpu_util import TOL_FP64, dev, err_v, host, rel_to_max, state_err
 
 pytestmark = pytest.mark.gpu
 
@@ -216,27 +216,28 @@ def test_tgv_steps_parity(cells, nsteps):
     ud = dev(u0)
     s.step(ud, nsteps, cfl=0.5)
     got = host(ud)
-    mom = np.abs(ref[1:4]).max()
-    d = np.abs(got - ref).reshape(5, -1).max(axis=1)
-    scale = np.array([np.abs(ref[0]).max(), mom, mom, mom, np.abs(ref[4]).max()])
-    _say("tgv steps", cells, nsteps, d / scale)
-    assert np.all(d / scale <= 1e-12)
+    d = state_err(got, ref, 3)
+    _say("tgv steps", cells, nsteps, d)
+    assert np.all(d <= 1e-12)
 
 
-def test_sedov_steps_parity_small():
+@pytest.mark.parametrize("nsteps", [1, 3, 10])
+def test_sedov_steps_parity_small(nsteps):
+    """The shock-capturing RK path (the indicator emitted by each stage's epilogue, smoothed
+    in the next stage's prologue) against the oracle, per field at 1e-12."""
     cfg = inputs.scaled(inputs.workload("sedov_32"), cells=(8, 8, 8))
     o = oracle.Oracle(**cfg)
     s = dgx.Solver(**cfg)
     u0 = inputs.sedov(o.node_coords())
-    ref, _ = o.step(u0, 3, cfl=0.5)
+    ref, tref = o.step(u0, nsteps, cfl=0.5)
     ud = dev(u0)
-    s.step(ud, 3, cfl=0.5)
-    got = host(ud)
-    d = np.abs(got - ref).reshape(5, -1).max(axis=1) / np.abs(ref).reshape(5, -1).max(axis=1).clip(1e-300)
-    _say("sedov 3 steps rel", d)
-    # the momentum starts at zero; compare against the largest conserved magnitude instead
-    dd = np.abs(got - ref).max() / np.abs(ref).max()
-    assert dd <= 1e-11, dd
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.step(ud, nsteps, cfl=0.5, t=t)
+    assert s.check() == 0
+    d = state_err(host(ud), ref, 3)
+    _say("sedov", nsteps, "steps: state err", d)
+    assert np.all(d <= 1e-12), d
+    np.testing.assert_allclose(host(t)[0], tref, rtol=1e-13)
 
 
 def test_determinism():
@@ -277,6 +278,16 @@ def test_pointer_validation():
     assert "device" in L.dgx_last_error(s._h).decode()
     with pytest.raises(ValueError):
         s.rhs(u, torch.empty(10, dtype=torch.float64, device="cuda"))
+    # u and du that share part of their range (not the same pointer) are rejected too
+    n = s.nvar * s.num_nodes
+    big = torch.ones(2 * n, dtype=torch.float64, device="cuda")
+    for off in (n // 2, 1):
+        st = L.dgx_rhs(s._h, C.c_void_p(big.data_ptr()), C.c_void_p(big.data_ptr() + 8 * off),
+                       C.c_double(0))
+        assert st == 1 and "overlap" in L.dgx_last_error(s._h).decode()
+    st = L.dgx_rhs(s._h, C.c_void_p(big.data_ptr()), C.c_void_p(big.data_ptr() + 8 * n), C.c_double(0))
+    assert st == 0                          # adjacent, disjoint halves are fine
+    torch.cuda.synchronize()
 
 
 def test_step_counts_zero_and_negative():
