@@ -227,10 +227,15 @@ dgx_status dgx_profile_read(dgx_handle h, double *avg_ms, int64_t *launches, con
 typedef struct dgx_batch_s *dgx_batch;
 
 /* nruns configurations (host array, copied); every run is 3D, DGX_VOL_EC, DGX_SURF_LLF or
- * HLL, polydeg 3..5, with its own grid, extent and gamma; all share one precision.  Each
- * RK stage of all runs is one persistent launch over (run, element tile) work items, runs
- * of higher polydeg first; a step (per-run dt + 5 stages) is replayed from a captured
- * hipGraph.  The library owns each run's second state buffer and RK register. */
+ * HLL, polydeg 3..5, with its own grid, extent and gamma; all share one precision (the
+ * many independent instances of Section 2.3.3).  Each RK stage of all runs is one launch
+ * over (run, element tile) work items, runs of higher polydeg first.  The launch takes one
+ * block per work item unless the tuner (or dgx_batch_set_shape) picks a persistent grid
+ * whose blocks loop over the items; one block per item is the default and what the tuner
+ * normally keeps, since the persistent loop holds more registers live.  A step (per-run
+ * dt + 5 stages) is replayed from a captured hipGraph.  The library owns each run's second
+ * state buffer and RK register (they are not passed in: a stage reads its input buffer's
+ * face neighbours while it writes the other). */
 dgx_status dgx_batch_create(const dgx_config *cfgs, int32_t nruns, void *hip_stream,
                             dgx_batch *out);
 dgx_status dgx_batch_destroy(dgx_batch b);
@@ -245,9 +250,14 @@ dgx_status dgx_batch_step(dgx_batch b, double *const *u, int32_t nsteps, double 
 dgx_status dgx_batch_rhs(dgx_batch b, const double *const *u, double *const *du);
 /* Autotuner: time one right-hand side of every run (written into the library's RK
  * registers; the states u are only read) for each candidate tile shape (threads per block:
- * 256 or 512, i.e. elements per work item) and persistent grid (2, 4, 8, 16 blocks per CU,
+ * 256 or 512, i.e. elements per work item) and persistent grid (2, 4 or 8 blocks per CU,
  * or one block per work item) and keep the fastest.  budget_ms bounds the tuning time. */
 dgx_status dgx_batch_tune(dgx_batch b, double *const *u, int32_t budget_ms);
+/* Set the tile shape by hand: block = 256 or 512 threads; grid = 0 for one block per work
+ * item, or a positive multiple of 8 (8 XCDs): a grid smaller than the number of work items
+ * runs the persistent kernel, whose blocks loop over XCD-contiguous ranges of items.
+ * DGX_EINVAL otherwise.  Synchronises the stream and drops the captured step graph. */
+dgx_status dgx_batch_set_shape(dgx_batch b, int32_t block, int32_t grid);
 /* The current tile shape: threads per block and persistent blocks. */
 dgx_status dgx_batch_shape(dgx_batch b, int32_t *block, int32_t *grid);
 /* Synchronise and report (and clear) the non-physical-state flag of any run. */

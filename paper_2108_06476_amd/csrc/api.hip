@@ -224,6 +224,12 @@ dgx_status check_dev(dgx_handle h, const void* p, size_t bytes, const char* name
 
 size_t state_bytes(dgx_handle h) { return sizeof(double) * (size_t)h->NV * h->E * h->NN; }
 
+// Two byte ranges [a, a + n) and [b, b + n) share an address.
+bool overlap(const void* a, const void* b, size_t n) {
+  const char *p = (const char*)a, *q = (const char*)b;
+  return p < q + n && q < p + n;
+}
+
 // Timing of the dominant kernel: one event pair brackets a run of consecutive stage
 // launches (an event recorded between two kernels leaves the stream idle for microseconds),
 // and the pair's time is shared by the launches inside it.
@@ -657,7 +663,7 @@ dgx_status dgx_rhs(dgx_handle h, const double* u, double* du, double t) {
   if (!h) return DGX_EINVAL;
   CHKDEV(h, u, state_bytes(h), "u");
   CHKDEV(h, du, state_bytes(h), "du");
-  if (u == du) return fail(h, DGX_EINVAL, "u and du must not overlap");
+  if (overlap(u, du, state_bytes(h))) return fail(h, DGX_EINVAL, "u and du overlap");
   return enqueue_rhs(h, u, du, nullptr, t);
 }
 
@@ -668,7 +674,7 @@ dgx_status dgx_rhs_alpha(dgx_handle h, const double* u, const double* alpha, dou
   CHKDEV(h, u, state_bytes(h), "u");
   CHKDEV(h, du, state_bytes(h), "du");
   CHKDEV(h, alpha, sizeof(double) * h->E, "alpha");
-  if (u == du) return fail(h, DGX_EINVAL, "u and du must not overlap");
+  if (overlap(u, du, state_bytes(h))) return fail(h, DGX_EINVAL, "u and du overlap");
   return enqueue_rhs(h, u, du, alpha);
 }
 

@@ -1,8 +1,9 @@
 // batch.hip -- ensembles of independent solvers (dgx_batch_*): runs of different grid
-// sizes and polynomial degrees advanced together.  Each RK stage of all runs is one
-// persistent launch over (run, element tile) work items; a step (per-run time step + 5
-// stages) is replayed from a captured hipGraph.  The tile shape (block size) and the
-// persistent grid are chosen by timing the candidates on the batch (dgx_batch_tune).
+// sizes and polynomial degrees advanced together.  Each RK stage of all runs is one launch
+// over (run, element tile) work items: one block per item, or a persistent grid whose
+// blocks loop over the items; a step (per-run time step + 5 stages) is replayed from a
+// captured hipGraph.  The tile shape (block size) and the grid are chosen by timing the
+// candidates on the batch (dgx_batch_tune) or set by hand (dgx_batch_set_shape).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -314,8 +315,12 @@ dgx_status dgx_batch_step(dgx_batch b, double* const* u, int32_t nsteps, double 
 
 dgx_status dgx_batch_rhs(dgx_batch b, const double* const* u, double* const* du) {
   if (!b || !u || !du) return DGX_EINVAL;
-  for (int r = 0; r < b->nruns; ++r)
-    if (u[r] == du[r]) return bfail(b, DGX_EINVAL, "u and du must not overlap");
+  for (int r = 0; r < b->nruns; ++r) {
+    const size_t bytes = sizeof(double) * 5 * (size_t)b->nodes[r];
+    const char *pu = (const char*)u[r], *pd = (const char*)du[r];
+    if (pu < pd + bytes && pd < pu + bytes)
+      return bfail(b, DGX_EINVAL, "u[" + std::to_string(r) + "] and du[" + std::to_string(r) + "] overlap");
+  }
   dgx_status st = bind(b, const_cast<double* const*>(u), du, nullptr);
   if (st != DGX_OK) return st;
   BHIP(b, batch_stage(b->stream, b->bl, b->budget, b->grid, b->prec, EPI_RHS, 0, 0.0, 0.0, 0, 0));
@@ -382,6 +387,13 @@ dgx_status dgx_batch_check(dgx_batch b, int32_t* flag) {
   BHIP(b, hipMemset(b->flag_d, 0, sizeof(int)));
   *flag = f;
   return f ? DGX_ENONPHYS : DGX_OK;
+}
+
+dgx_status dgx_batch_set_shape(dgx_batch b, int32_t block, int32_t grid) {
+  if (!b) return DGX_EINVAL;
+  if (block != 256 && block != 512) return bfail(b, DGX_EINVAL, "block must be 256 or 512");
+  if (grid < 0 || grid % 8 != 0) return bfail(b, DGX_EINVAL, "grid must be 0 or a positive multiple of 8");
+  return set_shape(b, block, grid);
 }
 
 dgx_status dgx_batch_shape(dgx_batch b, int32_t* block, int32_t* grid) {

@@ -1,5 +1,5 @@
 // batch_kernels.h -- ensembles of independent 3D runs (uneven grids, polydeg 3..5)
-// advanced by one persistent launch per RK stage.
+// advanced by one launch per RK stage over the element tiles of all runs.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -9,7 +9,7 @@ namespace dgx {
 
 constexpr int BATCH_NMIN = 3, BATCH_NMAX = 5;
 
-// Everything a persistent block needs to process a tile of run r (device-resident array).
+// Everything a block needs to process a tile of run r (device-resident array).
 struct RunDesc {
   double* u;            // the caller's state (stage parity 0 reads it)
   double* u2;           // the library's second state buffer
@@ -33,8 +33,8 @@ struct BatchLaunch {
 };
 
 // Host launchers (batch_kernels.hip).  budget: threads per block (256 or 512); grid: number
-// of persistent blocks (a multiple of 8); kw: the RK stage writes k (0 in a step's last
-// stage).
+// of blocks (a multiple of 8; below the number of work items the blocks persist and loop
+// over them); kw: the RK stage writes k (0 in a step's last stage).
 hipError_t batch_stage(hipStream_t st, const BatchLaunch& b, int budget, int grid, int prec,
                        int epi, int cur, double A, double B, int emit_speed, int kw);
 hipError_t batch_maxspeed(hipStream_t st, const BatchLaunch& b, int budget, int grid);

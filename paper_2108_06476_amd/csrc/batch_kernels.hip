@@ -1,4 +1,4 @@
-// batch_kernels.hip -- persistent kernels of the ensemble API: every launch processes the
+// batch_kernels.hip -- stage kernels of the ensemble API: every launch processes the
 // element tiles of all runs (work items), each tile with the same stage body as the
 // single-run kernel, specialised per polydeg (3, 4, 5) behind a uniform branch.
 #include "batch_kernels.h"

@@ -24,7 +24,7 @@ EXPORTS = ["dgx_create", "dgx_destroy", "dgx_set_stream", "dgx_num_nodes", "dgx_
            "dgx_node_coords", "dgx_rhs", "dgx_indicator", "dgx_rhs_alpha", "dgx_max_dt",
            "dgx_step", "dgx_integrals", "dgx_check", "dgx_last_error", "dgx_profile_enable",
            "dgx_profile_read", "dgx_batch_create", "dgx_batch_destroy", "dgx_batch_num_nodes",
-           "dgx_batch_step", "dgx_batch_rhs", "dgx_batch_tune", "dgx_batch_shape",
+           "dgx_batch_step", "dgx_batch_rhs", "dgx_batch_tune", "dgx_batch_set_shape", "dgx_batch_shape",
            "dgx_batch_check", "dgx_batch_last_error", "dgx_create_curved", "dgx_geometry",
            "dgx_create_mhd"]
 
@@ -95,6 +95,7 @@ def lib():
             "dgx_batch_step": ([vp, C.POINTER(vp), C.c_int32, C.c_double, vp], C.c_int),
             "dgx_batch_rhs": ([vp, C.POINTER(vp), C.POINTER(vp)], C.c_int),
             "dgx_batch_tune": ([vp, C.POINTER(vp), C.c_int32], C.c_int),
+            "dgx_batch_set_shape": ([vp, C.c_int32, C.c_int32], C.c_int),
             "dgx_batch_shape": ([vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)], C.c_int),
             "dgx_batch_check": ([vp, C.POINTER(C.c_int32)], C.c_int),
             "dgx_batch_last_error": ([vp], C.c_char_p),
@@ -307,6 +308,12 @@ class Batch:
 
     def tune(self, us, budget_ms=2000):
         self._call("dgx_batch_tune", self._ptrs(us, "u"), C.c_int32(budget_ms))
+        return self.shape()
+
+    def set_shape(self, block, grid):
+        """block: 256 or 512 threads; grid: 0 (one block per work item) or a multiple of 8
+        (persistent blocks when below the number of work items)."""
+        self._call("dgx_batch_set_shape", C.c_int32(block), C.c_int32(grid))
         return self.shape()
 
     def shape(self):
