@@ -131,6 +131,18 @@ dgx_status dgx_rhs_alpha(dgx_handle h, const double *u, const double *alpha, dou
  * device scalar *dt (Section 3.1: local wave speed, relative grid size, CFL). */
 dgx_status dgx_max_dt(dgx_handle h, const double *u, double cfl, double *dt);
 
+/* dgx_max_dt without any device allocation, for callers that cannot allocate (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same result
+ * as dgx_max_dt (bitwise: the same kernels in the same order), with the per-element
+ * partials in a static device array of the library, 2^20 float64 (8 MiB) per device, which
+ * each device that the library runs on keeps until the process ends.  The call allocates
+ * nothing and frees nothing; the handle (created beforehand, on the current device) and
+ * the arguments are as for dgx_max_dt.  DGX_EINVAL when the handle has more than 2^20
+ * elements or the current device is not the handle's.  Every call on one device shares
+ * that array: calls that overlap on one device (other streams, other host threads, other
+ * handles) race and must be ordered by the caller. */
+dgx_status dgx_max_dt_noalloc(dgx_handle h, const double *u, double cfl, double *dt);
+
 /* Advance u in place by nsteps Carpenter-Kennedy 5-stage 4th-order 2N-storage
  * steps: per step dt from u at its start (cfl > 0) or dt_fixed (cfl <= 0), then
  * for s = 1..5: k <- A_s k + dt R(u), u <- u + B_s k.  t (device scalar, may be

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -128,6 +129,32 @@ __global__ void k_zero_int(int* p) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
+// Scratch of dgx_max_dt_noalloc: the per-element wave-speed partials, in a file-scope
+// device array (each device holds its own copy for the life of the process).  Host code
+// never uses the name as an address: the device address comes from hipGetSymbolAddress,
+// taken once per device when a handle is created on it.
+constexpr int64_t NOALLOC_MAX_ELEMS = (int64_t)1 << 20;   // 8 MiB of float64
+static __device__ __align__(256) double scratch[NOALLOC_MAX_ELEMS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+double* scratch_ptr[MAX_DEVICES] = {};
+
+// The device address of `scratch` on device `dev` (the current device), looked up on the
+// first call for that device.
+hipError_t scratch_address(int dev, double** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace dgx
 
 using namespace dgx;
@@ -175,6 +202,8 @@ struct dgx_solver {
   std::vector<int> ev_count;   // stage launches inside each event pair
   int64_t launches = 0;
   double prof_ms = 0.0;
+  int device = 0;                    // the device the handle was created on
+  double* noalloc_partial = nullptr; // that device's static scratch (dgx_max_dt_noalloc)
 };
 
 namespace {
@@ -469,6 +498,13 @@ dgx_status create_impl(const dgx_config& c, const dgx_curv_config* cv, void* hip
     delete h;
     return DGX_EUNSUPPORTED;
   }
+  // set-up of dgx_max_dt_noalloc: the device address of this device's static scratch
+  if (hipGetDevice(&h->device) != hipSuccess ||
+      scratch_address(h->device, &h->noalloc_partial) != hipSuccess) {
+    (void)hipGetLastError();
+    delete h;
+    return DGX_EHIP;
+  }
   // curvilinear: the reference element's tables (2/h = 1); the metric terms carry the scale
   const double href[3] = {2.0, 2.0, 2.0};
 
@@ -697,6 +733,31 @@ dgx_status dgx_max_dt(dgx_handle h, const double* u, double cfl, double* dt) {
   CHKDEV(h, dt, sizeof(double), "dt");
   HIPCHK(h, enqueue_maxspeed(h, u));
   hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, h->stream, h->partial, h->npart, cfl,
+                     (double)(h->N + 1), dt, (double*)nullptr, (double*)nullptr);
+  HIPCHK(h, hipGetLastError());
+  return DGX_OK;
+}
+
+dgx_status dgx_max_dt_noalloc(dgx_handle h, const double* u, double cfl, double* dt) {
+  if (!h) return DGX_EINVAL;
+  if (!(cfl > 0.0)) return fail(h, DGX_EINVAL, "cfl must be > 0");
+  if (h->E > NOALLOC_MAX_ELEMS)
+    return fail(h, DGX_EINVAL, "dgx_max_dt_noalloc: " + std::to_string(h->E) +
+                                   " elements exceed its static scratch of " +
+                                   std::to_string(NOALLOC_MAX_ELEMS));
+  int dev = -1;
+  HIPCHK(h, hipGetDevice(&dev));
+  if (dev != h->device)
+    return fail(h, DGX_EINVAL, "dgx_max_dt_noalloc: the current device is not the handle's");
+  CHKDEV(h, u, state_bytes(h), "u");
+  CHKDEV(h, dt, sizeof(double), "dt");
+  // every partial in [0, E) is written by the first kernel before the second reads it, so
+  // nothing needs clearing
+  double* part = h->noalloc_partial;
+  HIPCHK(h, h->mhd      ? h->L->maxspeed_mhd(h->stream, u, part, h->g)
+            : h->curved ? h->L->maxspeed_curv(h->stream, u, part, h->g)
+                        : h->L->maxspeed(h->stream, u, part, h->g));
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, h->stream, part, h->E, cfl,
                      (double)(h->N + 1), dt, (double*)nullptr, (double*)nullptr);
   HIPCHK(h, hipGetLastError());
   return DGX_OK;

@@ -22,6 +22,7 @@ STATUS = {0: "DGX_OK", 1: "DGX_EINVAL", 2: "DGX_EHIP", 3: "DGX_ENOMEM", 4: "DGX_
 # every symbol declared in include/dgx.h
 EXPORTS = ["dgx_create", "dgx_destroy", "dgx_set_stream", "dgx_num_nodes", "dgx_num_elements",
            "dgx_node_coords", "dgx_rhs", "dgx_indicator", "dgx_rhs_alpha", "dgx_max_dt",
+           "dgx_max_dt_noalloc",
            "dgx_step", "dgx_integrals", "dgx_check", "dgx_last_error", "dgx_profile_enable",
            "dgx_profile_read", "dgx_batch_create", "dgx_batch_destroy", "dgx_batch_num_nodes",
            "dgx_batch_step", "dgx_batch_rhs", "dgx_batch_tune", "dgx_batch_set_shape", "dgx_batch_shape",
@@ -83,6 +84,7 @@ def lib():
             "dgx_indicator": ([vp, vp, vp, vp, vp], C.c_int),
             "dgx_rhs_alpha": ([vp, vp, vp, vp], C.c_int),
             "dgx_max_dt": ([vp, vp, C.c_double, vp], C.c_int),
+            "dgx_max_dt_noalloc": ([vp, vp, C.c_double, vp], C.c_int),
             "dgx_step": ([vp, vp, C.c_int32, C.c_double, C.c_double, vp], C.c_int),
             "dgx_integrals": ([vp, vp, vp, vp], C.c_int),
             "dgx_check": ([vp, C.POINTER(C.c_int32)], C.c_int),
@@ -227,6 +229,13 @@ class Solver:
         out = torch.empty(1, dtype=torch.float64, device="cuda") if out is None else out
         self._call("dgx_max_dt", _ptr(u, "u", self.nvar * self.num_nodes), C.c_double(cfl),
                    _ptr(out, "dt"))
+        return out
+
+    def max_dt_noalloc(self, u, cfl, out):
+        """dgx_max_dt into the caller's device scalar `out` (float64 [1]); the library
+        allocates nothing for it (its partials live in a static device array)."""
+        self._call("dgx_max_dt_noalloc", _ptr(u, "u", self.nvar * self.num_nodes),
+                   C.c_double(cfl), _ptr(out, "dt", 1))
         return out
 
     def step(self, u, nsteps, cfl=0.5, dt_fixed=0.0, t=None):
