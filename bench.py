@@ -58,10 +58,12 @@ WARMUP_FLOOR_S = 0.5   # warm-up runs at least this long, whatever --warmup says
 REPS = 5               # timed repetitions: the paper's best of 5 (Section 3.1), plus the median
 
 
-def warm_up(run_steps, warmup, floor_s=WARMUP_FLOOR_S):
-    """Run `warmup` steps, then more until `floor_s` seconds of stepping have passed, so the
-    clocks and caches have settled before the first timed repetition."""
+def warm_up(run_steps, warmup, floor_s=None):
+    """Run `warmup` steps, then more until `floor_s` seconds (default WARMUP_FLOOR_S) of
+    stepping have passed, so the clocks and caches have settled before the first timed
+    repetition."""
     import torch
+    floor_s = WARMUP_FLOOR_S if floor_s is None else floor_s
     t0 = time.perf_counter()
     run_steps(max(warmup, 1))
     torch.cuda.synchronize()
@@ -86,7 +88,7 @@ def timed_reps(run_steps, steps, reps=REPS):
     return out
 
 
-def time_steps(solver, u, steps, warmup, reps=REPS, t=None):
+def time_steps(solver, u, steps, warmup, reps=REPS, t=None, floor_s=None):
     """Warm-up, then `reps` timed repetitions of `steps` RK steps on the product path (one
     dgx_step call per repetition: step pairs replayed from the handle's captured graph).
     The warm-up runs on u itself (the graph is captured for that pointer) and u (and t) are
@@ -96,7 +98,7 @@ def time_steps(solver, u, steps, warmup, reps=REPS, t=None):
     run = lambda n: solver.step(u, n, cfl=0.5, t=t)
     u0 = u.clone()
     t0 = None if t is None else t.clone()
-    w = warm_up(run, warmup)
+    w = warm_up(run, warmup, floor_s)
     u.copy_(u0)
     if t is not None:
         t.copy_(t0)
@@ -207,6 +209,7 @@ def bench_rhs_graph(s, u, reps=20, replays=40):
 
 
 def main():
+    global WARMUP_FLOOR_S
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
@@ -217,6 +220,16 @@ def main():
     ap.add_argument("--variants", default="rhs,mixed,batched,sedov,weak,curved,mhd,dwave",
                     help="comma list of extra variants: rhs, mixed, batched, sedov, weak, "
                          "curved, mhd, dwave ('' for none)")
+    ap.add_argument("--volume", default=None, help="override the main line's volume integral "
+                    "(ec, central, shockcap_hg, weak, weak_mfma)")
+    ap.add_argument("--surface", default=None, help="override the main line's surface flux")
+    ap.add_argument("--precision", default=None, help="override the main line's precision")
+    ap.add_argument("--warmup-floor", type=float, default=WARMUP_FLOOR_S,
+                    help="seconds of warm-up at least (0 under a profiler)")
+    ap.add_argument("--rhs-only", action="store_true",
+                    help="profiling: time --steps right-hand-side evaluations (dgx_rhs) of the "
+                         "main line's configuration instead of RK steps, and stop there (for "
+                         "volume-only or surface-only configurations, which may not step)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -229,11 +242,23 @@ def main():
 
     from paper_2108_06476_amd import dgx, inputs
     torch.cuda.set_device(0)
-    cfg = inputs.workload(args.workload)
+    WARMUP_FLOOR_S = args.warmup_floor
+    cfg = dict(inputs.workload(args.workload))
+    for key in ("volume", "surface", "precision"):
+        if getattr(args, key) is not None:
+            cfg[key] = getattr(args, key)
     s = dgx.Solver(**cfg)
     u = make_state(s, args.workload)
     nodes = s.num_nodes
-    _log(f"workload {args.workload}: E={s.E} nodes={nodes}")
+    pkey = profile_key(args.workload, cfg)
+    _log(f"workload {args.workload} ({pkey}): E={s.E} nodes={nodes}")
+    if args.rhs_only:
+        secs = min(time_rhs(s, u, args.steps, args.warmup) for _ in range(3))
+        print(json.dumps({"metric": "DOF-RHS evals/sec, right-hand side only (profiling)",
+                          "value": args.steps * nodes / secs, "unit": "DOF-RHS/s",
+                          "config": {"workload": describe(args.workload, cfg)},
+                          "rhs_per_rep": args.steps, "best_of": 3}), flush=True)
+        return
 
     secs, secs_med, warm_s = time_steps(s, u, args.steps, args.warmup)
     value = args.steps * 5 * nodes / secs
@@ -249,12 +274,12 @@ def main():
     achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": stored_traffic("k_stage_tgv32_fp64"),
+                "traffic": stored_traffic(pkey),
                 "kernel": kname, "avg_ms": avg_ms, "launches": launches,
                 "timing": f"HIP events on the handle's stream, {prof_steps} profiled steps "
                           f"after the timed repetitions",
                 "alg_bytes_per_launch": alg_bytes}
-    valu = valu_object(stored_pmc("k_stage_tgv32_fp64"), avg_ms)
+    valu = valu_object(stored_pmc(pkey), avg_ms)
     _log(f"step: {secs / args.steps * 1e3:.4f} ms/step (min of {REPS}; median "
          f"{secs_med / args.steps * 1e3:.4f}), {value:.4e} DOF-RHS/s; {kname} avg "
          f"{avg_ms * 1e3:.2f} us over {launches} launches")
@@ -264,10 +289,9 @@ def main():
            "ms_per_step": secs / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "repetitions": REPS, "value_median": args.steps * 5 * nodes / secs_med,
            "ms_per_step_median": secs_med / args.steps * 1e3, "warmup_s": round(warm_s, 3),
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "tgv_32: 3D Euler Taylor-Green vortex Mach 0.1 + 1% seeded "
-                                  "density perturbation, DGSEM N=3, 32^3 periodic hex elements on "
-                                  "[-pi,pi]^3, EC volume + LLF surface, CK(5,4) RK at CFL 0.5",
+           "vs_baseline": None, "dtype": "f64" if cfg.get("precision", "fp64") == "fp64" else "f64+f32",
+           "data": "synthetic",
+           "config": {"workload": describe(args.workload, cfg),
                       "elements": s.E, "polydeg": 3, "dof_per_var": nodes,
                       "parallelism": "single GPU"},
            "pid_s": 1.0 / value, "roofline": roofline, "valu_fp64": valu,
@@ -371,10 +395,39 @@ def bench_batched(args, precision="fp64"):
     if b.check():
         raise RuntimeError("non-physical state in the ensemble")
     b.close()
-    return {"value": steps * 5 * total / min(secs), "unit": "DOF-RHS/s", "runs": len(runs),
+    del us
+    single = single_run_reference(runs, precision)
+    value = steps * 5 * total / min(secs)
+    return {"value": value, "unit": "DOF-RHS/s", "runs": len(runs),
             "value_median": steps * 5 * total / statistics.median(secs), "best_of": 3,
             "dof_per_var": total, "steps": steps, "precision": precision,
-            "tile_threads": shape[0], "grid_blocks": shape[1], "tune_s": round(tune_s, 2)}
+            "tile_threads": shape[0], "grid_blocks": shape[1], "tune_s": round(tune_s, 2),
+            "single_run_node_weighted": single, "vs_single_runs": round(value / single["value"], 4)}
+
+
+def single_run_reference(runs, precision, steps=4):
+    """The ensemble's work done run by run: each (K, N) pair of the ensemble timed as one
+    single-run dgx_step (best of 3 after a short warm-up), combined with the ensemble's node
+    counts: value = total nodes / sum over pairs of (nodes of the pair / single-run rate)."""
+    from paper_2108_06476_amd import dgx, inputs
+    pairs = {}
+    for r in runs:
+        pairs.setdefault((r["K"], r["N"]), []).append(r)
+    total, secs_per_rhs = 0, 0.0
+    rates = {}
+    for (K, N), rs in sorted(pairs.items()):
+        c = dict(inputs.ensemble_config(rs[0]), precision=precision)
+        s = dgx.Solver(**c)
+        u = inputs.ensemble_state(rs[0], s.node_coords()).contiguous()
+        tmin, _, _ = time_steps(s, u, steps, 2, reps=3, floor_s=0.2)
+        rate = steps * 5 * s.num_nodes / tmin
+        rates[f"K{K}_N{N}"] = round(rate / 1e9, 3)
+        nodes = s.num_nodes * len(rs)
+        total += nodes
+        secs_per_rhs += nodes / rate
+        s.close()
+    return {"value": total / secs_per_rhs, "unit": "DOF-RHS/s",
+            "rate_e9_by_pair": rates, "steps": steps}
 
 
 def bench_sedov(args):
@@ -462,6 +515,36 @@ def bench_mhd(args, name, volume="weak"):
         gbs = 8 * 8 * 3.6 * s.num_nodes / (avg_ms * 1e-3) / 1e9
         out.update(stage_us=round(avg_ms * 1e3, 2), stage_hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
     return out
+
+
+WORKLOAD_TEXT = {
+    "tgv_32": "3D Euler Taylor-Green vortex Mach 0.1 + 1% seeded density perturbation, DGSEM "
+              "N=3, 32^3 periodic hex elements on [-pi,pi]^3",
+    "sedov_32": "3D Euler Sedov-type Gaussian blast (width 0.25), DGSEM N=3, 32^3 periodic hex "
+                "elements on [-1,1]^3, Hennemann-Gassner indicator (alpha_max 0.5) with blended "
+                "DG/FV subcell volume",
+    "tgv_64_mixed": "3D Euler Taylor-Green vortex Mach 0.1, DGSEM N=3, 64^3 hex elements",
+    "tgv_n7_32_mixed": "3D Euler Taylor-Green vortex Mach 0.1, DGSEM N=7, 32^3 hex elements",
+    "density_wave_2d": "2D Euler density wave, DGSEM N=3, 16^2 periodic quads on [-2,2]^2",
+}
+
+
+def describe(workload, cfg):
+    """The workload of the main line in words (configuration overrides included)."""
+    return (f"{workload}: {WORKLOAD_TEXT.get(workload, workload)}; volume {cfg['volume']}, "
+            f"surface {cfg['surface']}, {cfg.get('precision', 'fp64')}, CK(5,4) RK at CFL 0.5")
+
+
+def profile_key(workload, cfg):
+    """Name of the committed counter summary that applies to the main line's stage kernel:
+    k_stage_<workload>_<precision> for the workload's own scheme, with the volume and surface
+    appended when they were overridden."""
+    from paper_2108_06476_amd import inputs
+    base = inputs.workload(workload)
+    key = "k_stage_" + workload.replace("_", "") + "_" + cfg.get("precision", "fp64")
+    if cfg["volume"] != base["volume"] or cfg["surface"] != base["surface"]:
+        key += f"_{cfg['volume']}_{cfg['surface']}"
+    return key
 
 
 def kernel_source_hash():
