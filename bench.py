@@ -58,10 +58,12 @@ WARMUP_FLOOR_S = 0.5   # warm-up runs at least this long, whatever --warmup says
 REPS = 5               # timed repetitions: the paper's best of 5 (Section 3.1), plus the median
 
 
-def warm_up(run_steps, warmup, floor_s=None):
+def warm_up(run_steps, warmup, floor_s=None, reset=None):
     """Run `warmup` steps, then more until `floor_s` seconds (default WARMUP_FLOOR_S) of
     stepping have passed, so the clocks and caches have settled before the first timed
-    repetition."""
+    repetition.  reset() (if given) runs after every chunk: the state then never moves more
+    than one chunk of steps away from its initial value (a long warm-up on a small mesh
+    would otherwise integrate far beyond the configured run)."""
     import torch
     floor_s = WARMUP_FLOOR_S if floor_s is None else floor_s
     t0 = time.perf_counter()
@@ -69,8 +71,12 @@ def warm_up(run_steps, warmup, floor_s=None):
     torch.cuda.synchronize()
     chunk = max(warmup, 10)
     while time.perf_counter() - t0 < floor_s:
+        if reset is not None:
+            reset()
         run_steps(chunk)
         torch.cuda.synchronize()
+    if reset is not None:
+        reset()
     return time.perf_counter() - t0
 
 
@@ -92,16 +98,21 @@ def time_steps(solver, u, steps, warmup, reps=REPS, t=None, floor_s=None):
     """Warm-up, then `reps` timed repetitions of `steps` RK steps on the product path (one
     dgx_step call per repetition: step pairs replayed from the handle's captured graph).
     The warm-up runs on u itself (the graph is captured for that pointer) and u (and t) are
-    then restored, so the timed steps start from the configured initial state (a long
-    warm-up on a small mesh would otherwise integrate far beyond it).
+    restored after every warm-up chunk, so the timed steps start from the configured initial
+    state.
     Returns (min seconds, median seconds, warm-up seconds)."""
     run = lambda n: solver.step(u, n, cfl=0.5, t=t)
     u0 = u.clone()
     t0 = None if t is None else t.clone()
-    w = warm_up(run, warmup, floor_s)
-    u.copy_(u0)
-    if t is not None:
-        t.copy_(t0)
+
+    def reset():
+        u.copy_(u0)
+        if t is not None:
+            t.copy_(t0)
+
+    w = warm_up(run, warmup, floor_s, reset)
+    if solver.check():
+        raise RuntimeError("non-physical state during the warm-up")
     del u0
     secs = timed_reps(run, steps, reps)
     if solver.check():
@@ -419,7 +430,7 @@ def single_run_reference(runs, precision, steps=4):
         c = dict(inputs.ensemble_config(rs[0]), precision=precision)
         s = dgx.Solver(**c)
         u = inputs.ensemble_state(rs[0], s.node_coords()).contiguous()
-        tmin, _, _ = time_steps(s, u, steps, 2, reps=3, floor_s=0.2)
+        tmin, _, _ = time_steps(s, u, steps, 2, reps=3, floor_s=min(0.2, WARMUP_FLOOR_S))
         rate = steps * 5 * s.num_nodes / tmin
         rates[f"K{K}_N{N}"] = round(rate / 1e9, 3)
         nodes = s.num_nodes * len(rs)

@@ -741,10 +741,11 @@ __device__ __forceinline__ void indicator_elem(double* w0, double* w1, double* w
     t2 = w2[0];
   }
   if (active && node == last) {
-    const double r1 = t0 != 0.0 ? (t0 - t1) / t0 : 0.0;
-    const double r2 = t1 != 0.0 ? (t1 - t2) / t1 : 0.0;
+    // the ratios and the logistic with refined hardware reciprocals (full float64 accuracy)
+    const double r1 = t0 != 0.0 ? (t0 - t1) * rcp_nr(t0) : 0.0;
+    const double r2 = t1 != 0.0 ? (t1 - t2) * rcp_nr(t1) : 0.0;
     const double en = fmax(r1, r2);
-    double al = 1.0 / (1.0 + exp(-sharp * (en - thr)));
+    double al = rcp_nr(1.0 + exp(-sharp * (en - thr)));
     if (al < alpha_min) al = 0.0;
     else if (al > 1.0 - alpha_min) al = 1.0;
     al = fmin(al, alpha_max);
@@ -965,9 +966,9 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
       double* w = reinterpret_cast<double*>(s.xb + (le < S::NE ? le : 0) * SS::SLOT);
       elem_sync<DIM, N>();   // the epilogue is done with the slot
       if (active) {
-        Prim<double> q;
-        if (!cons_to_prim<DIM>(un, g.gamma, q)) *g.flag = 1;
-        w[node] = q.rho * q.p;
+        double q;
+        if (!rho_p<DIM>(un, g.gamma, q)) *g.flag = 1;
+        w[node] = q;
       }
       indicator_elem<DIM, N>(w, w + NN, w + 2 * NN, sT + TAB_VINV, node, inb, active, a.ind_thr,
                              a.ind_sharp, a.ind_amin, a.ind_amax, a.alpha_next, nullptr, e);
@@ -1012,9 +1013,9 @@ __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_indicator(
     double um[S::NV];
 #pragma unroll
     for (int v = 0; v < S::NV; ++v) um[v] = u[v * ENN + e * NN + node];
-    Prim<double> q;
-    if (!cons_to_prim<DIM>(um, g.gamma, q)) *g.flag = 1;
-    sa[base + node] = q.rho * q.p;
+    double q;
+    if (!rho_p<DIM>(um, g.gamma, q)) *g.flag = 1;
+    sa[base + node] = q;
   }
   __syncthreads();   // V^-1
   indicator_elem<DIM, N>(sa + base, sb + base, sc + base, sV, node, le < S::NE, active, thr,

@@ -132,6 +132,18 @@ __device__ __forceinline__ bool cons_to_prim(const double (&u)[DIM + 2], double 
   return (q.rho > 0.0) && (q.p > 0.0) && (q.p < 1.0e300) && (q.rho < 1.0e300);
 }
 
+// The shock indicator's variable q = rho p of a conserved state, formed without a division:
+// rho p = (gamma - 1) (rho (rho E) - |rho v|^2 / 2).  Returns false for a non-physical state
+// (rho <= 0, p <= 0, or not finite).
+template <int DIM>
+__device__ __forceinline__ bool rho_p(const double (&u)[DIM + 2], double gamma, double& q) {
+  double m2 = u[1] * u[1];
+#pragma unroll
+  for (int k = 2; k <= DIM; ++k) m2 = fma(u[k], u[k], m2);
+  q = (gamma - 1.0) * fma(u[0], u[DIM + 1], -0.5 * m2);
+  return (u[0] > 0.0) && (q > 0.0) && (q < 1.0e300) && (u[0] < 1.0e300);
+}
+
 // Entropy-conservative, kinetic-energy-preserving two-point flux in direction D:
 //   f_rho  = {{rho}}_ln {{v_D}},  f_rhov = f_rho {{v}} + {{p}} e_D,
 //   f_rhoE = f_rho (1/((gamma-1) {{rho/p}}_ln) + v_L.v_R/2) + (p_L v_DR + p_R v_DL)/2.
