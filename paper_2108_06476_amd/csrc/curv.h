@@ -307,6 +307,123 @@ __global__ __launch_bounds__((Shape<3, N>::THREADS)) void k_stage_curv(StageArgs
   stage_tile_curv<N, VOL, EPI>(s, sT, a, g, (int)xcd_tile(blockIdx.x, gridDim.x));
 }
 
+// Small curvilinear meshes: a stage of a few elements is a chain of single-wave latencies (the
+// paper's 4^3 mesh has 64 elements for 1,024 SIMDs).  Here four waves share one element of
+// 4^3 nodes (lane = node in every wave) and divide its work:
+//   wave 0: x faces, x pair round;  wave 1: y faces, y pair round, source term;
+//   wave 2: z faces, the packed x/y half round;  wave 3: z pair round and z half round.
+// Before the block barrier the waves stage what the others read (wave d < 3: the metric
+// vectors Ja^d and its faces' neighbour states; wave 3: the primitives).  Each wave adds its
+// partner shares and then its own node's sum into its own LDS slot (one wave's LDS operations
+// complete in issue order); wave 0 sums the four slots in a fixed order, scales by 1/J, adds
+// the source and runs the epilogue.
+template <int VOL>
+struct CurvSplitLds {
+  double rho[64], v[3][64], p[64], beta[64];
+  double ja[9][64];
+  double u[VOL == VOL_CENTRAL ? 5 : 1][VOL == VOL_CENTRAL ? 64 : 1];
+  double x[4][5][64];   // per-wave accumulators
+  double src[5][64];    // source term at the nodes
+};
+
+constexpr int CURV_SPLIT_MAX_E = 512;   // element count up to which the split kernel runs
+
+template <int VOL, int EPI>
+__global__ __launch_bounds__(256) void k_stage_curv_split(StageArgs a, Geom g) {
+  constexpr int N = 3, NN = 64, NV = 5;
+  __shared__ CurvSplitLds<VOL> s;
+  __shared__ double sT[TAB_SIZE];
+  for (int i = threadIdx.x; i < TAB_SIZE; i += blockDim.x) sT[i] = g.tab[i];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave (uniform)
+  const int node = (int)(threadIdx.x & 63u);
+  const int e = blockIdx.x;
+  const unsigned ENN = (unsigned)g.E * NN;
+  const unsigned own_ix = (unsigned)e * NN + node;
+  double um[NV], un[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) um[v] = (a.uin + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
+  if (w < 3) {
+    if (a.surf != SURF_NONE) {
+      int ec[3];
+      elem_xyz(g, e, ec);
+      if (w == 0) face_load<3, N, 0>(a.uin, g, e, ec, node, un);
+      else if (w == 1) face_load<3, N, 1>(a.uin, g, e, ec, node, un);
+      else face_load<3, N, 2>(a.uin, g, e, ec, node, un);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.ja[w * 3 + k][node] = g.ja[(w * 3 + k) * ENN + own_ix];
+  }
+  Prim<double> qd;
+  if (!cons_to_prim<3>(um, g.gamma, qd)) *g.flag = 1;
+  if (w == 3) {
+    s.rho[node] = qd.rho;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s.v[k][node] = VOL == VOL_CENTRAL ? qd.v[k] : 0.5 * qd.v[k];
+    s.p[node] = qd.p;
+    s.beta[node] = qd.beta;
+    if constexpr (VOL == VOL_CENTRAL) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) s.u[v][node] = um[v];
+    }
+  }
+  double* x = &s.x[w][0][0];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v * NN + node] = 0.0;
+  __syncthreads();   // tables, metric vectors, primitives and zeroed slots visible
+
+  double acc[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+  if (a.surf != SURF_NONE && w < 3) {
+    if (w == 0) surface_dir_curv<N, 0>(s, g, a.surf, node, node, um, qd, un, sT + TAB_LIFT, acc);
+    else if (w == 1) surface_dir_curv<N, 1>(s, g, a.surf, node, node, um, qd, un, sT + TAB_LIFT, acc);
+    else surface_dir_curv<N, 2>(s, g, a.surf, node, node, um, qd, un, sT + TAB_LIFT, acc);
+  }
+  if constexpr (VOL != VOL_NONE) {
+    const double hme[3] = {0.5 * qd.v[0], 0.5 * qd.v[1], 0.5 * qd.v[2]};
+    const double* sS = sT + TAB_S;
+    if (w == 0) volume_dir_curv<N, 0, VOL, false>(s, x, true, 0, node, qd, hme, um, sS, g.inv_gm1, acc);
+    else if (w == 1) volume_dir_curv<N, 1, VOL, false>(s, x, true, 0, node, qd, hme, um, sS, g.inv_gm1, acc);
+    else if (w == 2) volume_xy_half_curv<N, VOL>(s, x, true, 0, node, qd, hme, um, sS, g.inv_gm1, acc);
+    else volume_dir_curv<N, 2, VOL, true>(s, x, true, 0, node, qd, hme, um, sS, g.inv_gm1, acc);
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) lds_add(&x[v * NN + node], acc[v]);
+  if (w == 1) {
+    double src[NV] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (g.source) {
+      const double ts = a.t0 ? *a.t0 + a.cs * *a.dt : a.t;
+      mms_source(g.gamma, g.xyz[own_ix], g.xyz[ENN + own_ix], g.xyz[2 * ENN + own_ix], ts, src);
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s.src[v][node] = src[v];
+  }
+  __syncthreads();   // every wave's shares, own sums and the source have landed
+  if (w != 0) return;
+  const double ij = rcp_nr(g.jac[own_ix]);
+  double R[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v)
+    R[v] = (((s.x[0][v][node] + s.x[1][v][node]) + s.x[2][v][node]) + s.x[3][v][node]) * ij +
+           s.src[v][node];
+  // wave 0 alone: the epilogue's element-wide reductions are wave reductions
+  stage_epilogue<3, N, 5, EPI, 256>(
+      nullptr, a, g, 0, node, e, true, true, ENN, own_ix, um, R,
+      [&](const double (&unew)[5], double (&ls)[3]) {
+        Prim<double> q;
+        const bool ok = cons_to_prim<3, false>(unew, g.gamma, q);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          double ad[3];
+          ja_of(s, d, node, ad);
+          const double va = q.v[0] * ad[0] + q.v[1] * ad[1] + q.v[2] * ad[2];
+          const double al = sqrt_pos(ad[0] * ad[0] + ad[1] * ad[1] + ad[2] * ad[2]);
+          ls[d] = (fabs(va) + q.c * al) * ij;
+        }
+        return ok;
+      });
+}
+
 // Geometry of one element per block (one thread per node): positions from Eq. (2) at the
 // mapped LGL points of the reference box [-1,1]^3 (cells K per direction), J and the
 // curl-form metric terms.  Dm: the LGL differentiation matrix [n][n].

@@ -123,6 +123,12 @@ struct Launch {
 
   template <int VOL, int EPI>
   static hipError_t stage_curv1(hipStream_t st, const StageArgs& a, const Geom& g) {
+    if constexpr (N == 3) {
+      if (g.E <= CURV_SPLIT_MAX_E) {   // small meshes: four waves per element
+        hipLaunchKernelGGL((k_stage_curv_split<VOL, EPI>), dim3((unsigned)g.E), dim3(256), 0, st, a, g);
+        return hipGetLastError();
+      }
+    }
     hipLaunchKernelGGL((k_stage_curv<N, VOL, EPI>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st, a, g);
     return hipGetLastError();
   }

@@ -20,7 +20,7 @@ import torch
 import oracle
 from paper_2108_06476_amd import dgx, inputs
 
-from gpu_util import TOL_FP64, dev, dissipation_max, host, phys_flux_max
+from gpu_util import TOL_FP64, dev, dissipation_max, host, phys_flux_max, state_err
 
 pytestmark = pytest.mark.gpu
 
@@ -111,6 +111,30 @@ def test_curv_paper_mesh(N):
     tol = _tol(o, s)
     print(f"paper mesh N={N}: err {e} tol {tol:.2e}", flush=True)
     assert np.all(e <= tol), e
+
+
+@pytest.mark.parametrize("K", [4, 9])
+@pytest.mark.parametrize("vol,surf", [("ec", "llf"), ("ec", "hll"), ("central", "ec"), ("none", "llf")])
+def test_curv_small_and_large_mesh_kernels(K, vol, surf):
+    """N = 3: up to 512 elements the stage runs four waves per element (the paper's 4^3 mesh),
+    beyond it one wave per element (K = 9: 729 elements); both against the oracle, the RHS at a
+    nonzero time and 4 steps."""
+    o, s = _pair(3, K, vol=vol, surf=surf)
+    u = _state(o, "smooth", 40 + K)
+    e = _err(host(s.rhs(dev(u), t=0.3)), o.rhs(u, 0.3), u, o, 0.3)
+    tol = _tol(o, s)
+    print(f"K={K} {vol}/{surf}: err {e} tol {tol:.2e}", flush=True)
+    assert np.all(e <= tol), e
+    u0 = o.initial(0.0)
+    ref, tref = o.step(u0, 4, cfl=0.5, t=0.0)
+    ud = dev(u0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.step(ud, 4, cfl=0.5, t=t)
+    d = state_err(host(ud), ref, 3)
+    print(f"K={K} {vol}/{surf}: 4 steps state err {d}", flush=True)
+    assert np.all(d <= 1e-12), d
+    np.testing.assert_allclose(float(t.item()), tref, rtol=1e-13)
+    assert s.check() == 0
 
 
 def test_curv_free_stream():
