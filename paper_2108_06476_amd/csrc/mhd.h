@@ -455,6 +455,106 @@ __global__ __launch_bounds__((Shape<3, N>::THREADS), 3) void k_stage_mhd_ec(Stag
 }
 
 // CFL partial per element: sum_d (2/h_d) max_nodes (|v_d| + c_f,d).
+// Small meshes: a stage of a few elements is a chain of single-wave latencies (the 4^3
+// Alfven-wave mesh has 64 elements for 1,024 SIMDs).  Three waves share one element of 4^3
+// nodes (lane = node in every wave) and wave d takes direction d: its face term, so that the
+// three neighbour loads are in flight together, and its volume term (the weak form's staged
+// f^d contraction, or the entropy-conservative pair rounds along d with Powell's term).  Each
+// wave adds its partner shares and then its own sum into its own LDS slot (one wave's LDS
+// operations complete in issue order); wave 0 sums the three slots in a fixed order and runs
+// the epilogue.
+template <int VOL>
+struct MhdSplitLds {
+  MhdEcLds<(VOL == VOL_EC ? 64 : 1), 16> nd;    // EC: node data of the pair flux
+  MhdLds<(VOL == VOL_EC ? 1 : 64), 16> f[3];   // weak form: each wave's staged fluxes
+  double x[3][8][64];                           // per-wave sums
+};
+
+constexpr int MHD_SPLIT_MAX_E = 512;   // element count up to which the split kernel runs
+
+template <int VOL, int EPI>
+__global__ __launch_bounds__(192) void k_stage_mhd_split(StageArgs a, Geom g) {
+  constexpr int N = 3, NN = 64;
+  __shared__ MhdSplitLds<VOL> s;
+  __shared__ double sT[TAB_SIZE];
+  for (int i = threadIdx.x; i < TAB_SIZE; i += blockDim.x) sT[i] = g.tab[i];
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave (uniform)
+  const int node = (int)(threadIdx.x & 63u);
+  const int e = blockIdx.x;
+  const unsigned ENN = (unsigned)g.E * NN;
+  const unsigned own_ix = (unsigned)e * NN + node;
+  double um[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) um[v] = (a.uin + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
+  MhdPrim qm;
+  if (!mhd_prim(um, g.gamma, qm)) *g.flag = 1;
+  int ec[3];
+  elem_xyz(g, e, ec);
+  double* x = &s.x[w][0][0];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) x[v * NN + node] = 0.0;
+  double R[8];
+#pragma unroll
+  for (int v = 0; v < 8; ++v) R[v] = 0.0;
+  if constexpr (VOL == VOL_EC) {
+    const MhdNode me = mhd_node(qm);
+    double phi[8];
+    phi[0] = 0.0;
+    phi[4] = me.vB;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      phi[1 + k] = me.B[k];
+      phi[5 + k] = me.v[k];
+    }
+    if (w == 0) {
+      s.nd.rho[node] = me.rho;
+      s.nd.beta[node] = me.beta;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        s.nd.v[k][node] = me.v[k];
+        s.nd.B[k][node] = me.B[k];
+      }
+      s.nd.v2[node] = me.v2;
+      s.nd.B2[node] = me.B2;
+      s.nd.vB[node] = me.vB;
+    }
+    __syncthreads();   // tables, node data and zeroed slots visible
+    const double* sS = sT + TAB_S;
+    if (w == 0) {
+      if (a.surf != SURF_NONE) mhd_ec_face<N, 0>(g, a, sT, e, ec, node, um, qm, me, phi, R);
+      mhd_ec_dir<N, 0>(s.nd, x, true, 0, node, me, phi, sS, g.inv_gm1, R);
+    } else if (w == 1) {
+      if (a.surf != SURF_NONE) mhd_ec_face<N, 1>(g, a, sT, e, ec, node, um, qm, me, phi, R);
+      mhd_ec_dir<N, 1>(s.nd, x, true, 0, node, me, phi, sS, g.inv_gm1, R);
+    } else {
+      if (a.surf != SURF_NONE) mhd_ec_face<N, 2>(g, a, sT, e, ec, node, um, qm, me, phi, R);
+      mhd_ec_dir<N, 2>(s.nd, x, true, 0, node, me, phi, sS, g.inv_gm1, R);
+    }
+  } else {
+    __syncthreads();   // tables and zeroed slots visible
+    if (w == 0) mhd_dir<N, 0>(s.f[0], g, a, sT, true, e, ec, 0, node, um, qm, R);
+    else if (w == 1) mhd_dir<N, 1>(s.f[1], g, a, sT, true, e, ec, 0, node, um, qm, R);
+    else mhd_dir<N, 2>(s.f[2], g, a, sT, true, e, ec, 0, node, um, qm, R);
+  }
+#pragma unroll
+  for (int v = 0; v < 8; ++v) lds_add(&x[v * NN + node], R[v]);
+  __syncthreads();   // every wave's shares and own sums have landed
+  if (w != 0) return;
+#pragma unroll
+  for (int v = 0; v < 8; ++v) R[v] = (s.x[0][v][node] + s.x[1][v][node]) + s.x[2][v][node];
+  // wave 0 alone: the epilogue's element-wide reductions are wave reductions
+  stage_epilogue<3, N, 8, EPI, 256>(
+      nullptr, a, g, 0, node, e, true, true, ENN, own_ix, um, R,
+      [&](const double (&un)[8], double (&ls)[3]) {
+        MhdPrim q;
+        const bool ok = mhd_prim(un, g.gamma, q);
+        ls[0] = sT[TAB_JAC + 0] * (fabs(q.v[0]) + mhd_cf<0>(q));
+        ls[1] = sT[TAB_JAC + 1] * (fabs(q.v[1]) + mhd_cf<1>(q));
+        ls[2] = sT[TAB_JAC + 2] * (fabs(q.v[2]) + mhd_cf<2>(q));
+        return ok;
+      });
+}
+
 template <int N>
 __global__ __launch_bounds__((Shape<3, N>::THREADS)) void k_maxspeed_mhd(
     const double* __restrict__ u, double* __restrict__ partial, Geom g) {

@@ -169,6 +169,19 @@ struct Launch {
 
   static hipError_t stage_mhd(hipStream_t st, const StageArgs& a, const Geom& g, int vol, int epi) {
     if constexpr (DIM == 3) {
+      if constexpr (N == 3) {
+        if (g.E <= MHD_SPLIT_MAX_E) {   // small meshes: three waves per element
+          const dim3 eg((unsigned)g.E), eb(192);
+          if (vol == VOL_EC) {
+            if (epi == EPI_RK) hipLaunchKernelGGL((k_stage_mhd_split<VOL_EC, EPI_RK>), eg, eb, 0, st, a, g);
+            else hipLaunchKernelGGL((k_stage_mhd_split<VOL_EC, EPI_RHS>), eg, eb, 0, st, a, g);
+          } else {
+            if (epi == EPI_RK) hipLaunchKernelGGL((k_stage_mhd_split<VOL_WEAK, EPI_RK>), eg, eb, 0, st, a, g);
+            else hipLaunchKernelGGL((k_stage_mhd_split<VOL_WEAK, EPI_RHS>), eg, eb, 0, st, a, g);
+          }
+          return hipGetLastError();
+        }
+      }
       const dim3 grid(blocks(g.E)), block(S::THREADS);
       if (vol == VOL_EC) {
         if (epi == EPI_RK) hipLaunchKernelGGL((k_stage_mhd_ec<N, EPI_RK>), grid, block, 0, st, a, g);

@@ -144,3 +144,27 @@ def test_mhd_ec_steps_and_thin_grid():
 def test_mhd_ec_rejects_ec_surface_with_weak_volume():
     with pytest.raises(dgx.DgxError):
         dgx.MhdSolver(3, 2, surface="ec", volume="weak")
+
+
+@pytest.mark.parametrize("K", [4, 9])
+@pytest.mark.parametrize("vol,surf", [("weak", "hll"), ("weak", "llf"), ("ec", "ec"),
+                                      ("ec", "llf"), ("ec", "hll")])
+def test_mhd_small_and_large_mesh_kernels(K, vol, surf):
+    """N = 3 runs three waves per element up to 512 elements (4^3) and one wave per element
+    above (9^3): the right-hand side at a nodal-jump state and four RK steps of the Alfven
+    wave against the oracle on both."""
+    o = oracle.MhdOracle(3, K, surface=surf, volume=vol)
+    s = dgx.MhdSolver(3, K, surface=surf, volume=vol)
+    u = _states(o, "nodal", 40 + K)
+    e = np.abs(host(s.rhs(dev(u))) - o.rhs(u)).reshape(8, -1).max(axis=1) / _scale(u, 2.0 / K)
+    print(f"K={K} {vol}/{surf}: err {e}", flush=True)
+    assert np.all(e <= TOL_FP64), e
+    u0 = o.alfven(0.0)
+    ref, tref = o.step(u0, 4, cfl=0.5)
+    ud = dev(u0)
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s.step(ud, 4, cfl=0.5, t=t)
+    d = np.abs(host(ud) - ref).max() / np.abs(ref).max()
+    assert d <= 1e-12, d
+    np.testing.assert_allclose(float(t.item()), tref, rtol=1e-13)
+    assert s.check() == 0
