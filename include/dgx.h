@@ -146,7 +146,12 @@ dgx_status dgx_max_dt_noalloc(dgx_handle h, const double *u, double cfl, double 
 /* Advance u in place by nsteps Carpenter-Kennedy 5-stage 4th-order 2N-storage
  * steps: per step dt from u at its start (cfl > 0) or dt_fixed (cfl <= 0), then
  * for s = 1..5: k <- A_s k + dt R(u), u <- u + B_s k.  t (device scalar, may be
- * NULL) is advanced by every dt.  The stage register lives in library scratch.  Pairs of
+ * NULL) is advanced by every dt.  Ownership differs from a 2N-storage call in which the
+ * caller passes k: the handle owns k and a second state buffer (two state-sized arrays,
+ * 168 MB at 32^3 elements, N = 3), because every stage reads the face neighbours of its
+ * input state while it writes the updated state, so it writes into the other buffer; ten
+ * stages (two steps) bring the result back to u, and an odd step count ends with one copy
+ * into u.  Pairs of
  * steps are replayed from a hipGraph that the handle captures once per (u, t, cfl,
  * dt_fixed) and keeps; the result is bitwise that of launching every kernel (which the
  * handle does while profiling is enabled). */

@@ -186,6 +186,38 @@ def _speeds(u, d, dim):
     return v[d], c
 
 
+def _flux_jacobian(u, d, dim):
+    """df_d/du by central differences of the oracle's physical flux (step 1e-6 per column)."""
+    n = dim + 2
+    A = np.zeros((n, n))
+    for j in range(n):
+        h = 1e-6 * max(1.0, abs(u[j]))
+        up, um = u.copy(), u.copy()
+        up[j] += h
+        um[j] -= h
+        A[:, j] = (oracle.flux_phys(up, d, dim, G) - oracle.flux_phys(um, d, dim, G)) / (2 * h)
+    return A
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_wave_speeds_are_flux_jacobian_eigenvalues(dim):
+    """The speeds in the HLL and LLF pins below, v_d -+ c with c = sqrt(gamma p / rho), are
+    the extreme eigenvalues of the flux Jacobian df_d/du (eigenvalues of a difference
+    Jacobian of the physical flux), and the others equal v_d; so those pins do not rest on
+    a restated sound speed."""
+    rng = np.random.default_rng(91 + dim)
+    for _ in range(50):
+        u = _rand_state(dim, rng, jump=3.0)
+        for d in range(dim):
+            lam = np.linalg.eigvals(_flux_jacobian(u, d, dim))
+            v, c = _speeds(u, d, dim)
+            tol = 1e-6 * (abs(v) + c)
+            assert np.abs(lam.imag).max() < tol
+            ev = np.sort(lam.real)
+            np.testing.assert_allclose([ev[0], ev[-1]], [v - c, v + c], rtol=0, atol=tol)
+            np.testing.assert_allclose(ev[1:-1], v, rtol=0, atol=tol)
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_hll_intermediate_state(dim):
     """HLL = f_L + s_L (u* - u_L) = f_R + s_R (u* - u_R) with the integral-average state

@@ -95,12 +95,16 @@ def test_entropy_conservation_ec_ec(dim, N):
     o = oracle.Oracle(**_cfg(dim, N, 3, "ec", "ec"))
     for u in (_smooth(o, 5), _nodal(o, 5)):
         du = o.rhs(u)
-        rate = o.integrals(u, du)[6]
-        # scale: sum J w |w(u)| . |R|
+        # dS/dt = sum J w_node w(u) . R, with the entropy variables pinned as the gradient of
+        # the entropy; the oracle's own entropy-rate output must agree with it
         wv = np.stack([oracle.entropy_vars(u[:, e, n], dim, G)
                        for e in range(o.E) for n in range(o.NN)], axis=1)
-        scale = np.sum(_weights(o).reshape(-1) * np.sum(np.abs(wv) * np.abs(du.reshape(o.nvar, -1)), 0))
+        Jw = _weights(o).reshape(-1)
+        R = du.reshape(o.nvar, -1)
+        rate = np.sum(Jw * np.sum(wv * R, 0))
+        scale = np.sum(Jw * np.sum(np.abs(wv) * np.abs(R), 0))   # sum J w |w(u)| . |R|
         assert abs(rate) < 1e-13 * scale, rate / scale
+        assert abs(o.integrals(u, du)[6] - rate) < 1e-13 * scale
 
 
 @pytest.mark.parametrize("dim", [2, 3])
