@@ -178,8 +178,8 @@ __device__ __forceinline__ void surface_dir_curv(const L& s, const Geom& g, int 
   qR.beta = plus ? qn.beta : qm.beta;
   qL.c = plus ? qm.c : qn.c;
   qR.c = plus ? qn.c : qm.c;
-  surface_flux_vec(surf, uL, qL, uR, qR, a, g.gamma, F);
-  const double c = plus ? sL[2 * D + 1] : sL[2 * D];
+  const double half = surface_flux_vec(surf, uL, qL, uR, qR, a, g.inv_gm1, F);
+  const double c = half * (plus ? sL[2 * D + 1] : sL[2 * D]);
 #pragma unroll
   for (int v = 0; v < 5; ++v) R[v] += c * F[v];
 }

@@ -166,13 +166,17 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t nb) {
   return x * per + (x < rem ? x : rem) + i;
 }
 
+// The interface flux itself (factor applied): the subcell fluxes are shared through LDS.
 template <int DIM, int D>
 __device__ __forceinline__ void face_flux(int surf, const double (&uL)[DIM + 2], const Prim<double>& L,
                                           const double (&uR)[DIM + 2], const Prim<double>& R,
                                           double gamma, double (&f)[DIM + 2]) {
-  if (surf == SURF_LLF) llf_flux<DIM, D>(uL, L, uR, R, gamma, f);
-  else if (surf == SURF_HLL) hll_flux<DIM, D>(uL, L, uR, R, gamma, f);
+  double c = 1.0;
+  if (surf == SURF_LLF) c = llf_flux<DIM, D>(uL, L, uR, R, gamma, f);
+  else if (surf == SURF_HLL) c = hll_flux<DIM, D>(uL, L, uR, R, gamma, f);
   else ec_flux<DIM, D, double>(L, R, 1.0 / (gamma - 1.0), f);
+#pragma unroll
+  for (int v = 0; v < DIM + 2; ++v) f[v] *= c;
 }
 
 // --------------------------------------------------------------------------------------
@@ -421,7 +425,7 @@ __device__ __forceinline__ void face_load(const double* __restrict__ u, const Ge
   for (int v = 0; v < NV; ++v) un[v] = (ub + (size_t)v * ENN)[(unsigned)oth];
 }
 
-template <int DIM, int N, int D>
+template <int DIM, int N, int D, bool PREF>
 __device__ __forceinline__ void surface_dir(const Geom& g, int surf, int node,
                                             const double (&um)[DIM + 2], const Prim<double>& qm,
                                             const double (&un)[DIM + 2], const double* sL,
@@ -436,16 +440,18 @@ __device__ __forceinline__ void surface_dir(const Geom& g, int surf, int node,
                                   : cons_to_prim<DIM, false>(un, g.gamma, qn);
   if (!ok) *g.flag = 1;
   double F[NV];
+  double half = 1.0;   // F holds the flux divided by half (LLF: 1/2, HLL: 1/(s_R - s_L))
   if (surf == SURF_LLF) {
-    // (f_L + f_R)/2 - lambda (u_R - u_L)/2 from (own, neighbour): the sign s of the jump
+    // 2 F = (f_L + f_R) - lambda (u_R - u_L) from (own, neighbour): the sign of the jump
     // term makes both elements' evaluations identical bit for bit
     double fo[NV], fn[NV];
     phys_flux<DIM, D>(um, qm, fo);
     phys_flux<DIM, D>(un, qn, fn);
     const double lam = fmax(fabs(qm.v[D]) + qm.c, fabs(qn.v[D]) + qn.c);
-    const double hl = (plus ? 0.5 : -0.5) * lam;
+    const double sl = plus ? lam : -lam;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) F[v] = 0.5 * (fo[v] + fn[v]) - hl * (un[v] - um[v]);
+    for (int v = 0; v < NV; ++v) F[v] = (fo[v] + fn[v]) - sl * (un[v] - um[v]);
+    half = 0.5;
   } else if (surf == SURF_EC) {
     ec_flux_sym<DIM, D>(qm, qn, g.inv_gm1, F);
   } else {
@@ -467,14 +473,15 @@ __device__ __forceinline__ void surface_dir(const Geom& g, int surf, int node,
     qR.p = plus ? qn.p : qm.p;
     qL.c = plus ? qm.c : qn.c;
     qR.c = plus ? qn.c : qm.c;
-    hll_flux<DIM, D>(uL, qL, uR, qR, g.gamma, F);
+    half = hll_flux<DIM, D>(uL, qL, uR, qR, g.gamma, F);
   }
-  // pref: the constant pressure left out of a float32 volume sum (0 in float64), removed
-  // from the lifted normal momentum flux with it
-  F[1 + D] -= pref;
-  const double c = plus ? sL[2 * D + 1] : sL[2 * D];
+  const double c0 = plus ? sL[2 * D + 1] : sL[2 * D];
+  const double c = half * c0;
 #pragma unroll
   for (int v = 0; v < NV; ++v) R[v] += c * F[v];
+  // PREF: the constant pressure pref left out of a float32 volume sum, removed from the
+  // lifted normal momentum flux with it
+  if constexpr (PREF) R[1 + D] -= c0 * pref;
 }
 
 struct StageArgs {
@@ -867,9 +874,10 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
 
   // ---- surface: each boundary node's face flux, lifted onto the node
   if (a.surf != SURF_NONE && active) {
-    surface_dir<DIM, N, 0>(g, a.surf, node, um, qd, unb[0], sT + TAB_LIFT, pref, R);
-    surface_dir<DIM, N, 1>(g, a.surf, node, um, qd, unb[1], sT + TAB_LIFT, pref, R);
-    if constexpr (DIM == 3) surface_dir<DIM, N, 2>(g, a.surf, node, um, qd, unb[2], sT + TAB_LIFT, pref, R);
+    constexpr bool PREF = sizeof(RT) == 4;
+    surface_dir<DIM, N, 0, PREF>(g, a.surf, node, um, qd, unb[0], sT + TAB_LIFT, pref, R);
+    surface_dir<DIM, N, 1, PREF>(g, a.surf, node, um, qd, unb[1], sT + TAB_LIFT, pref, R);
+    if constexpr (DIM == 3) surface_dir<DIM, N, 2, PREF>(g, a.surf, node, um, qd, unb[2], sT + TAB_LIFT, pref, R);
   }
 
   // ---- volume

@@ -55,32 +55,34 @@ __device__ __forceinline__ double mhd_cf(const MhdPrim& q) {
 
 // Interface flux along D from the minus-side state L to the plus side R (HLL or LLF).
 template <int D>
-__device__ __forceinline__ void mhd_surface_flux(int surf, const double (&uL)[8], const MhdPrim& L,
-                                                 const double (&uR)[8], const MhdPrim& R,
-                                                 double (&f)[8]) {
+__device__ __forceinline__ double mhd_surface_flux(int surf, const double (&uL)[8], const MhdPrim& L,
+                                                   const double (&uR)[8], const MhdPrim& R,
+                                                   double (&f)[8]) {
   double fL[8], fR[8];
   mhd_flux<D>(uL, L, fL);
   mhd_flux<D>(uR, R, fR);
   const double cL = mhd_cf<D>(L), cR = mhd_cf<D>(R);
-  if (surf == SURF_LLF) {
+  if (surf == SURF_LLF) {   // twice the flux: factor 1/2
     const double lam = fmax(fabs(L.v[D]) + cL, fabs(R.v[D]) + cR);
 #pragma unroll
-    for (int v = 0; v < 8; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
-    return;
+    for (int v = 0; v < 8; ++v) f[v] = (fL[v] + fR[v]) - lam * (uR[v] - uL[v]);
+    return 0.5;
   }
   const double sL = fmin(L.v[D] - cL, R.v[D] - cR);
   const double sR = fmax(L.v[D] + cL, R.v[D] + cR);
   if (sL >= 0.0) {
 #pragma unroll
     for (int v = 0; v < 8; ++v) f[v] = fL[v];
-  } else if (sR <= 0.0) {
+    return 1.0;
+  }
+  if (sR <= 0.0) {
 #pragma unroll
     for (int v = 0; v < 8; ++v) f[v] = fR[v];
-  } else {
-    const double inv = 1.0 / (sR - sL);
-#pragma unroll
-    for (int v = 0; v < 8; ++v) f[v] = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) * inv;
+    return 1.0;
   }
+#pragma unroll
+  for (int v = 0; v < 8; ++v) f[v] = sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v]);
+  return rcp_nr(sR - sL);   // the division, left to the caller's lift coefficient
 }
 
 template <int NE_NN, int XB>
@@ -136,8 +138,8 @@ __device__ __forceinline__ void mhd_dir(L& s, const Geom& g, const StageArgs& a,
         uL[v] = plus ? um[v] : un[v];
         uR[v] = plus ? un[v] : um[v];
       }
-      mhd_surface_flux<D>(a.surf, uL, plus ? qm : qn, uR, plus ? qn : qm, F);
-      const double c = plus ? sT[TAB_LIFT + 2 * D + 1] : sT[TAB_LIFT + 2 * D];
+      const double cf = mhd_surface_flux<D>(a.surf, uL, plus ? qm : qn, uR, plus ? qn : qm, F);
+      const double c = cf * (plus ? sT[TAB_LIFT + 2 * D + 1] : sT[TAB_LIFT + 2 * D]);
 #pragma unroll
       for (int v = 0; v < 8; ++v) R[v] += c * F[v];
     }
@@ -347,6 +349,7 @@ __device__ __forceinline__ void mhd_ec_face(const Geom& g, const StageArgs& a, c
   for (int v = 0; v < 8; ++v) un[v] = (a.uin + (size_t)v * ENN)[off];
   MhdPrim qn;
   if (!mhd_prim(un, g.gamma, qn)) *g.flag = 1;
+  double cf = 1.0;   // F holds the flux divided by cf
   if (a.surf == SURF_EC) {
     const MhdNode nn = mhd_node(qn);
     mhd_ec_flux<D>(plus ? me : nn, plus ? nn : me, g.inv_gm1, F);
@@ -356,12 +359,12 @@ __device__ __forceinline__ void mhd_ec_face(const Geom& g, const StageArgs& a, c
       uL[v] = plus ? um[v] : un[v];
       uR[v] = plus ? un[v] : um[v];
     }
-    mhd_surface_flux<D>(a.surf, uL, plus ? qm : qn, uR, plus ? qn : qm, F);
+    cf = mhd_surface_flux<D>(a.surf, uL, plus ? qm : qn, uR, plus ? qn : qm, F);
   }
-  const double Bf = 0.5 * (qm.B[D] + qn.B[D]);
   const double c = plus ? sT[TAB_LIFT + 2 * D + 1] : sT[TAB_LIFT + 2 * D];
+  const double cF = c * cf, cB = c * (0.5 * (qm.B[D] + qn.B[D]));
 #pragma unroll
-  for (int v = 0; v < 8; ++v) R[v] += c * (F[v] + phi[v] * Bf);
+  for (int v = 0; v < 8; ++v) R[v] += cF * F[v] + cB * phi[v];
 }
 
 // Three waves per SIMD: the register budget of 168 costs a few spilled bytes, which the

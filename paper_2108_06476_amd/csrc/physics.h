@@ -260,25 +260,32 @@ __device__ __forceinline__ void central_flux(const double (&uL)[DIM + 2], const 
   for (int v = 0; v < DIM + 2; ++v) f[v] = 0.5 * (fL[v] + fR[v]);
 }
 
+// The interface fluxes below return f up to a scalar factor, which they return: the flux is
+// factor * f.  A caller that scales the result anyway (the lift) folds the factor into its
+// coefficient and saves one multiplication per variable.
+
 // Local Lax-Friedrichs: (f_L + f_R)/2 - lambda (u_R - u_L)/2,
-// lambda = max(|v_DL| + c_L, |v_DR| + c_R).
+// lambda = max(|v_DL| + c_L, |v_DR| + c_R); f holds twice the flux (factor 1/2).
 template <int DIM, int D>
-__device__ __forceinline__ void llf_flux(const double (&uL)[DIM + 2], const Prim<double>& L,
-                                         const double (&uR)[DIM + 2], const Prim<double>& R,
-                                         double gamma, double (&f)[DIM + 2]) {
+__device__ __forceinline__ double llf_flux(const double (&uL)[DIM + 2], const Prim<double>& L,
+                                           const double (&uR)[DIM + 2], const Prim<double>& R,
+                                           double gamma, double (&f)[DIM + 2]) {
   double fL[DIM + 2], fR[DIM + 2];
   phys_flux<DIM, D>(uL, L, fL);
   phys_flux<DIM, D>(uR, R, fR);
   const double lam = fmax(fabs(L.v[D]) + L.c, fabs(R.v[D]) + R.c);
 #pragma unroll
-  for (int v = 0; v < DIM + 2; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
+  for (int v = 0; v < DIM + 2; ++v) f[v] = (fL[v] + fR[v]) - lam * (uR[v] - uL[v]);
+  return 0.5;
 }
 
-// HLL with s_L = min(v_DL - c_L, v_DR - c_R), s_R = max(v_DL + c_L, v_DR + c_R).
+// HLL with s_L = min(v_DL - c_L, v_DR - c_R), s_R = max(v_DL + c_L, v_DR + c_R): f_L for
+// s_L >= 0, f_R for s_R <= 0, else (s_R f_L - s_L f_R + s_L s_R (u_R - u_L)) / (s_R - s_L),
+// returned without the division (factor 1/(s_R - s_L)).
 template <int DIM, int D>
-__device__ __forceinline__ void hll_flux(const double (&uL)[DIM + 2], const Prim<double>& L,
-                                         const double (&uR)[DIM + 2], const Prim<double>& R,
-                                         double gamma, double (&f)[DIM + 2]) {
+__device__ __forceinline__ double hll_flux(const double (&uL)[DIM + 2], const Prim<double>& L,
+                                           const double (&uR)[DIM + 2], const Prim<double>& R,
+                                           double gamma, double (&f)[DIM + 2]) {
   double fL[DIM + 2], fR[DIM + 2];
   phys_flux<DIM, D>(uL, L, fL);
   phys_flux<DIM, D>(uR, R, fR);
@@ -287,15 +294,16 @@ __device__ __forceinline__ void hll_flux(const double (&uL)[DIM + 2], const Prim
   if (sL >= 0.0) {
 #pragma unroll
     for (int v = 0; v < DIM + 2; ++v) f[v] = fL[v];
-  } else if (sR <= 0.0) {
+    return 1.0;
+  }
+  if (sR <= 0.0) {
 #pragma unroll
     for (int v = 0; v < DIM + 2; ++v) f[v] = fR[v];
-  } else {
-    const double inv = 1.0 / (sR - sL);
-#pragma unroll
-    for (int v = 0; v < DIM + 2; ++v)
-      f[v] = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) * inv;
+    return 1.0;
   }
+#pragma unroll
+  for (int v = 0; v < DIM + 2; ++v) f[v] = sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v]);
+  return rcp_nr(sR - sL);
 }
 
 enum { SURF_LLF = 0, SURF_HLL = 1, SURF_EC = 2, SURF_NONE = 3 };
@@ -370,14 +378,16 @@ __device__ __forceinline__ void central_flux_vec(const double (&uL)[5], const Pr
 }
 
 // Interface flux through a face with contravariant vector a (from L to R): LLF and HLL
-// with the wave speeds scaled by |a| (|a| f*(u_L, u_R; a/|a|)), EC as ec_flux_vec.
-__device__ __forceinline__ void surface_flux_vec(int surf, const double (&uL)[5],
-                                                 const Prim<double>& L, const double (&uR)[5],
-                                                 const Prim<double>& R, const double (&a)[3],
-                                                 double gamma, double (&f)[5]) {
+// with the wave speeds scaled by |a| (|a| f*(u_L, u_R; a/|a|)), EC as ec_flux_vec.  Returns
+// the factor that turns f into the flux (as llf_flux and hll_flux; the caller folds it into
+// its lift coefficient): 0.5 for LLF, 1/(s_R - s_L) for HLL between its wave speeds, else 1.
+__device__ __forceinline__ double surface_flux_vec(int surf, const double (&uL)[5],
+                                                   const Prim<double>& L, const double (&uR)[5],
+                                                   const Prim<double>& R, const double (&a)[3],
+                                                   double inv_gm1, double (&f)[5]) {
   if (surf == SURF_EC) {
-    ec_flux_vec(L, R, a, 1.0 / (gamma - 1.0), f);
-    return;
+    ec_flux_vec(L, R, a, inv_gm1, f);
+    return 1.0;
   }
   double fL[5], fR[5];
   flux_vec(uL, L, a, fL);
@@ -388,22 +398,24 @@ __device__ __forceinline__ void surface_flux_vec(int surf, const double (&uL)[5]
   if (surf == SURF_LLF) {
     const double lam = fmax(fabs(vL) + L.c * al, fabs(vR) + R.c * al);
 #pragma unroll
-    for (int v = 0; v < 5; ++v) f[v] = 0.5 * (fL[v] + fR[v]) - 0.5 * lam * (uR[v] - uL[v]);
-    return;
+    for (int v = 0; v < 5; ++v) f[v] = (fL[v] + fR[v]) - lam * (uR[v] - uL[v]);
+    return 0.5;
   }
   const double sL = fmin(vL - L.c * al, vR - R.c * al);
   const double sR = fmax(vL + L.c * al, vR + R.c * al);
   if (sL >= 0.0) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) f[v] = fL[v];
-  } else if (sR <= 0.0) {
+    return 1.0;
+  }
+  if (sR <= 0.0) {
 #pragma unroll
     for (int v = 0; v < 5; ++v) f[v] = fR[v];
-  } else {
-    const double inv = 1.0 / (sR - sL);
-#pragma unroll
-    for (int v = 0; v < 5; ++v) f[v] = (sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v])) * inv;
+    return 1.0;
   }
+#pragma unroll
+  for (int v = 0; v < 5; ++v) f[v] = sR * fL[v] - sL * fR[v] + sL * sR * (uR[v] - uL[v]);
+  return rcp_nr(sR - sL);
 }
 
 // Source term of the manufactured solution rho = 2 + A sin(theta), theta = k (x+y+z) - om t,
