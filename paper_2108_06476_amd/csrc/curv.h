@@ -145,7 +145,7 @@ __device__ __forceinline__ void volume_xy_half_curv(const L& s, double* __restri
 
 // Face term along reference direction D for a boundary node: the interface flux through the
 // node's Ja^D (equal on both sides of the face), evaluated with the minus-side state first
-// so that both elements compute the same value, lifted with -+1/w.
+// so that both elements evaluate the same expression (equal to rounding), lifted with -+1/w.
 template <int N, int D, typename L>
 __device__ __forceinline__ void surface_dir_curv(const L& s, const Geom& g, int surf, int node,
                                                  int li, const double (&um)[5],

@@ -183,8 +183,9 @@ __device__ __forceinline__ void face_flux(int surf, const double (&uL)[DIM + 2],
 // One stage of the right-hand side, one thread per node, Shape::NE elements per block
 // (element-tiled, staged in LDS):
 //   surface: the thread of every face node evaluates the numerical flux with the neighbour's
-//            node across the face (each interface is evaluated by both of its elements from
-//            the same two states, so both get the same value) and lifts it to its node:
+//            node across the face (each interface is evaluated by both of its elements, from
+//            the same two states in the same order, so the two agree to rounding) and lifts
+//            it to its node:
 //            +(2/h_d)/w_0 F* at i_d = 0, -(2/h_d)/w_N F* at i_d = N;
 //   volume:  -(2/h_d) sum_{m != i_d} S_{i_d m} f#(u, u_m), each pair evaluated once;
 //   shock capturing: R_vol = (1 - alpha) R_DG + alpha R_FV (alpha = 0 skips the FV part);
@@ -404,8 +405,9 @@ __device__ __forceinline__ void fv_dir(const L& s, double* __restrict__ f, int f
 // Surface term of one node in direction D: a node with index_D = 0 (N) lies on the
 // element's minus (plus) face; it evaluates the numerical flux with the neighbour's node
 // across that face and lifts it, +(2/h_D)/w_0 F* (minus) or -(2/h_D)/w_N F* (plus).  Both
-// elements of an interface evaluate it from the same (left, right) states in the same
-// order, so they obtain the same value.
+// elements of an interface evaluate the same expression of the (left, right) states; the
+// primitives of the two states come from different code (the own node's from the staging,
+// the neighbour's here), so the two values agree to rounding, not always bit for bit.
 // Issue the loads of the neighbour's node across the face in direction D (if any).
 template <int DIM, int N, int D>
 __device__ __forceinline__ void face_load(const double* __restrict__ u, const Geom& g, int e,
@@ -442,8 +444,8 @@ __device__ __forceinline__ void surface_dir(const Geom& g, int surf, int node,
   double F[NV];
   double half = 1.0;   // F holds the flux divided by half (LLF: 1/2, HLL: 1/(s_R - s_L))
   if (surf == SURF_LLF) {
-    // 2 F = (f_L + f_R) - lambda (u_R - u_L) from (own, neighbour): the sign of the jump
-    // term makes both elements' evaluations identical bit for bit
+    // 2 F = (f_L + f_R) - lambda (u_R - u_L) from (own, neighbour): with the sign of the
+    // jump term both elements evaluate the same expression of (left, right)
     double fo[NV], fn[NV];
     phys_flux<DIM, D>(um, qm, fo);
     phys_flux<DIM, D>(un, qn, fn);
