@@ -75,13 +75,34 @@ static const double CK_C[5] = {0.0, 1432997174477.0 / 9575080441755.0,
                                2006345519317.0 / 3224310063776.0,
                                2802321613138.0 / 2924317926251.0};
 
-// dt = cfl * 2 / ((N+1) * max partial); t0 = t (the step's start time, when asked); t += dt
-__global__ __launch_bounds__(1024) void k_dt_final(const double* __restrict__ partial, int64_t np,
-                                                   double cfl, double n1, double* __restrict__ dt,
-                                                   double* __restrict__ t, double* __restrict__ t0) {
-  __shared__ double s[16];
-  const double m = block_max<1024>(partial, np, s);
-  if (threadIdx.x == 0) {
+// dt = cfl * 2 / ((N+1) * max partial); t0 = t (the step's start time, when asked); t += dt.
+// T = 1024 threads, or one wave (T = 64) for up to DT_WAVE_MAX partials: a small mesh's step
+// is a chain of short launches, and one wave reduces with DPP moves and no barrier.  max is
+// exact, so both give the same dt.
+constexpr int64_t DT_WAVE_MAX = 4096;
+
+template <int T>
+__global__ __launch_bounds__(T) void k_dt_final(const double* __restrict__ partial, int64_t np,
+                                                double cfl, double n1, double* __restrict__ dt,
+                                                double* __restrict__ t, double* __restrict__ t0) {
+  double m;
+  int owner;
+  if constexpr (T == 64) {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};   // four loads in flight per lane
+    int64_t i = threadIdx.x;
+    for (; i + 3 * 64 < np; i += 4 * 64) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a[k] = fmax(a[k], partial[i + k * 64]);
+    }
+    for (; i < np; i += 64) a[0] = fmax(a[0], partial[i]);
+    m = wave_max_lane63(fmax(fmax(a[0], a[1]), fmax(a[2], a[3])));
+    owner = 63;
+  } else {
+    __shared__ double s[T / 64];
+    m = block_max<T>(partial, np, s);
+    owner = 0;
+  }
+  if ((int)threadIdx.x == owner) {
     const double d = cfl * 2.0 / (n1 * m);
     *dt = d;
     if (t) {
@@ -89,6 +110,14 @@ __global__ __launch_bounds__(1024) void k_dt_final(const double* __restrict__ pa
       *t += d;
     }
   }
+}
+
+static void launch_dt_final(hipStream_t st, const double* partial, int64_t np, double cfl,
+                            double n1, double* dt, double* t, double* t0) {
+  if (np <= DT_WAVE_MAX)
+    hipLaunchKernelGGL(k_dt_final<64>, dim3(1), dim3(64), 0, st, partial, np, cfl, n1, dt, t, t0);
+  else
+    hipLaunchKernelGGL(k_dt_final<1024>, dim3(1), dim3(1024), 0, st, partial, np, cfl, n1, dt, t, t0);
 }
 
 __global__ void k_set_dt(double v, double* __restrict__ dt, double* __restrict__ t,
@@ -344,8 +373,7 @@ dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double 
   const bool adaptive = cfl > 0.0;
   double* t0 = h->g.source ? h->t0 : nullptr;   // step start time for the stage times
   if (adaptive) {
-    hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, h->stream, h->partial, h->npart, cfl,
-                       (double)(h->N + 1), h->dt, t, t0);
+    launch_dt_final(h->stream, h->partial, h->npart, cfl, (double)(h->N + 1), h->dt, t, t0);
   } else {
     hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, h->stream, dt_fixed, h->dt, t, t0);
   }
@@ -732,8 +760,7 @@ dgx_status dgx_max_dt(dgx_handle h, const double* u, double cfl, double* dt) {
   CHKDEV(h, u, state_bytes(h), "u");
   CHKDEV(h, dt, sizeof(double), "dt");
   HIPCHK(h, enqueue_maxspeed(h, u));
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, h->stream, h->partial, h->npart, cfl,
-                     (double)(h->N + 1), dt, (double*)nullptr, (double*)nullptr);
+  launch_dt_final(h->stream, h->partial, h->npart, cfl, (double)(h->N + 1), dt, nullptr, nullptr);
   HIPCHK(h, hipGetLastError());
   return DGX_OK;
 }
@@ -757,8 +784,7 @@ dgx_status dgx_max_dt_noalloc(dgx_handle h, const double* u, double cfl, double*
   HIPCHK(h, h->mhd      ? h->L->maxspeed_mhd(h->stream, u, part, h->g)
             : h->curved ? h->L->maxspeed_curv(h->stream, u, part, h->g)
                         : h->L->maxspeed(h->stream, u, part, h->g));
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(1024), 0, h->stream, part, h->E, cfl,
-                     (double)(h->N + 1), dt, (double*)nullptr, (double*)nullptr);
+  launch_dt_final(h->stream, part, h->E, cfl, (double)(h->N + 1), dt, nullptr, nullptr);
   HIPCHK(h, hipGetLastError());
   return DGX_OK;
 }
