@@ -173,6 +173,24 @@ def test_max_dt_parity(name):
     np.testing.assert_allclose(dt, o.max_dt(u, 0.5), rtol=1e-14)
 
 
+@pytest.mark.parametrize("cells", [(16, 16, 16), (16, 16, 17)])
+def test_max_dt_both_reduction_shapes(cells):
+    """The CFL reduction runs as one wave up to 4096 element partials and as a 1024-thread
+    block beyond: both at the boundary, against the oracle, with the fastest element (the
+    largest wave speed) placed in the last element, which a reduction that stopped short
+    would miss."""
+    cfg = inputs.scaled(inputs.workload("tgv_32"), cells=cells)
+    o = oracle.Oracle(**cfg)
+    s = dgx.Solver(**cfg)
+    u = inputs.tgv(o.node_coords())
+    u[1:4, -1, :] *= 3.0   # momentum of the last element: its wave speed is the largest
+    dt = host(s.max_dt(dev(u), 0.5))[0]
+    np.testing.assert_allclose(dt, o.max_dt(u, 0.5), rtol=1e-14)
+    u2 = u.copy()
+    u2[1:4, -1, :] /= 3.0
+    assert host(s.max_dt(dev(u2), 0.5))[0] > dt
+
+
 @pytest.mark.parametrize("dim", [2, 3])
 def test_integrals_parity(dim):
     cfg = _cfg(dim, 3, (4, 3, 2)[:dim], "ec", "llf")
