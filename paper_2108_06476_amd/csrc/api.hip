@@ -395,6 +395,7 @@ dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double 
       a.alpha_smooth = h->cfg.alpha_smooth;
       a.alpha_next = araw[(j + 1) % 2];
       indicator_constants(h->N, a.ind_thr, a.ind_sharp);
+      a.ind_xcut = indicator_xcut(h->cfg.alpha_min);
       a.ind_amin = h->cfg.alpha_min;
       a.ind_amax = h->cfg.alpha_max;
     }

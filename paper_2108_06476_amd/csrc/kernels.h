@@ -507,7 +507,7 @@ struct StageArgs {
   // shock capturing, RK: the raw indicator of the stage's output state (nullptr: skip) and
   // its constants (threshold, sharpness, alpha_min, alpha_max)
   double* alpha_next = nullptr;
-  double ind_thr = 0.0, ind_sharp = 0.0, ind_amin = 0.0, ind_amax = 0.0;
+  double ind_thr = 0.0, ind_sharp = 0.0, ind_amin = 0.0, ind_amax = 0.0, ind_xcut = 0.0;
   // shock capturing: the raw indicator of the stage's input (nullptr: alpha holds the
   // smoothed factors); each element then smooths its own from it and its face neighbours'
   const double* alpha_raw_in = nullptr;
@@ -685,7 +685,8 @@ template <int DIM, int N>
 __device__ __forceinline__ void indicator_elem(double* w0, double* w1, double* w2,
                                                const double* sV, int node, bool inb, bool active,
                                                double thr, double sharp, double alpha_min,
-                                               double alpha_max, double* __restrict__ alpha_raw,
+                                               double alpha_max, double xcut,
+                                               double* __restrict__ alpha_raw,
                                                double* __restrict__ energy, int64_t e) {
   constexpr int NN = Shape<DIM, N>::NN, n = N + 1;
   constexpr bool WAVE = WaveElem<DIM, N>::value;
@@ -754,9 +755,20 @@ __device__ __forceinline__ void indicator_elem(double* w0, double* w1, double* w
     const double r1 = t0 != 0.0 ? (t0 - t1) * rcp_nr(t0) : 0.0;
     const double r2 = t1 != 0.0 ? (t1 - t2) * rcp_nr(t1) : 0.0;
     const double en = fmax(r1, r2);
-    double al = rcp_nr(1.0 + exp(-sharp * (en - thr)));
-    if (al < alpha_min) al = 0.0;
-    else if (al > 1.0 - alpha_min) al = 1.0;
+    // the logistic 1/(1 + exp(-x)) lies below alpha_min for x < -xcut and above
+    // 1 - alpha_min for x > xcut (xcut = ln(1/alpha_min - 1)); beyond those by a margin the
+    // clipped value is known without the exponential
+    const double x = sharp * (en - thr);
+    double al;
+    if (x < -xcut - 1e-3) {
+      al = 0.0;
+    } else if (x > xcut + 1e-3) {
+      al = 1.0;
+    } else {
+      al = rcp_nr(1.0 + exp(-x));
+      if (al < alpha_min) al = 0.0;
+      else if (al > 1.0 - alpha_min) al = 1.0;
+    }
     al = fmin(al, alpha_max);
     alpha_raw[e] = al;
     if (energy) energy[e] = en;
@@ -981,7 +993,8 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
         w[node] = q;
       }
       indicator_elem<DIM, N>(w, w + NN, w + 2 * NN, sT + TAB_VINV, node, inb, active, a.ind_thr,
-                             a.ind_sharp, a.ind_amin, a.ind_amax, a.alpha_next, nullptr, e);
+                             a.ind_sharp, a.ind_amin, a.ind_amax, a.ind_xcut, a.alpha_next,
+                             nullptr, e);
     }
   }
 }
@@ -1007,7 +1020,7 @@ void k_stage(StageArgs a, Geom g) {
 template <int DIM, int N>
 __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_indicator(
     const double* __restrict__ u, double* __restrict__ alpha_raw, double* __restrict__ energy,
-    Geom g, double alpha_min, double alpha_max, double thr, double sharp) {
+    Geom g, double alpha_min, double alpha_max, double thr, double sharp, double xcut) {
   using S = Shape<DIM, N>;
   constexpr int NN = S::NN;
   __shared__ double sa[S::NE * NN], sb[S::NE * NN], sc[S::NE * NN];
@@ -1029,7 +1042,7 @@ __global__ __launch_bounds__((Shape<DIM, N>::THREADS)) void k_indicator(
   }
   __syncthreads();   // V^-1
   indicator_elem<DIM, N>(sa + base, sb + base, sc + base, sV, node, le < S::NE, active, thr,
-                         sharp, alpha_min, alpha_max, alpha_raw, energy, e);
+                         sharp, alpha_min, alpha_max, xcut, alpha_raw, energy, e);
 }
 
 // alpha_e = max(alpha_raw_e, max over face neighbours alpha_raw_nb / 2)

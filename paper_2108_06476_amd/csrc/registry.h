@@ -6,6 +6,7 @@
 #include "kernels.h"
 #include "curv.h"
 #include "mhd.h"
+#include <limits>
 
 namespace dgx {
 
@@ -16,6 +17,14 @@ enum { PREC_FP64 = 0, PREC_MIXED = 1 };
 inline void indicator_constants(int N, double& thr, double& sharp) {
   thr = 0.5 * std::pow(10.0, -1.8 * std::pow((double)(N + 1), 0.25));
   sharp = std::log((1.0 - 0.0001) / 0.0001) / thr;
+}
+
+// x beyond which the clipped logistic is known: 1/(1 + exp(-x)) < alpha_min for
+// x < -ln(1/alpha_min - 1) and > 1 - alpha_min for x > ln(1/alpha_min - 1); infinite (never
+// skip the exponential) unless 0 < alpha_min < 1/2.
+inline double indicator_xcut(double alpha_min) {
+  return (alpha_min > 0.0 && alpha_min < 0.5) ? std::log(1.0 / alpha_min - 1.0)
+                                              : std::numeric_limits<double>::infinity();
 }
 
 struct Launchers {
@@ -91,7 +100,7 @@ struct Launch {
     double thr, sharp;
     indicator_constants(N, thr, sharp);
     hipLaunchKernelGGL((k_indicator<DIM, N>), dim3(blocks(g.E)), dim3(S::THREADS), 0, st, u, ar,
-                       en, g, amin, amax, thr, sharp);
+                       en, g, amin, amax, thr, sharp, indicator_xcut(amin));
     return hipGetLastError();
   }
 
