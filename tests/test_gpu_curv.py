@@ -118,7 +118,7 @@ def test_curv_paper_mesh(N):
 def test_curv_small_and_large_mesh_kernels(K, vol, surf):
     """N = 3: up to 512 elements the stage runs four waves per element (the paper's 4^3 mesh),
     beyond it one wave per element (K = 9: 729 elements); both against the oracle, the RHS at a
-    nonzero time and 4 steps."""
+    nonzero time and 5 steps (two replayed step pairs, one launched step and the copy back)."""
     o, s = _pair(3, K, vol=vol, surf=surf)
     u = _state(o, "smooth", 40 + K)
     e = _err(host(s.rhs(dev(u), t=0.3)), o.rhs(u, 0.3), u, o, 0.3)
@@ -126,12 +126,12 @@ def test_curv_small_and_large_mesh_kernels(K, vol, surf):
     print(f"K={K} {vol}/{surf}: err {e} tol {tol:.2e}", flush=True)
     assert np.all(e <= tol), e
     u0 = o.initial(0.0)
-    ref, tref = o.step(u0, 4, cfl=0.5, t=0.0)
+    ref, tref = o.step(u0, 5, cfl=0.5, t=0.0)
     ud = dev(u0)
     t = torch.zeros(1, dtype=torch.float64, device="cuda")
-    s.step(ud, 4, cfl=0.5, t=t)
+    s.step(ud, 5, cfl=0.5, t=t)
     d = state_err(host(ud), ref, 3)
-    print(f"K={K} {vol}/{surf}: 4 steps state err {d}", flush=True)
+    print(f"K={K} {vol}/{surf}: 5 steps state err {d}", flush=True)
     assert np.all(d <= 1e-12), d
     np.testing.assert_allclose(float(t.item()), tref, rtol=1e-13)
     assert s.check() == 0

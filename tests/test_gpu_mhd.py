@@ -151,7 +151,7 @@ def test_mhd_ec_rejects_ec_surface_with_weak_volume():
                                       ("ec", "llf"), ("ec", "hll")])
 def test_mhd_small_and_large_mesh_kernels(K, vol, surf):
     """N = 3 runs three waves per element up to 512 elements (4^3) and one wave per element
-    above (9^3): the right-hand side at a nodal-jump state and four RK steps of the Alfven
+    above (9^3): the right-hand side at a nodal-jump state and five RK steps of the Alfven
     wave against the oracle on both."""
     o = oracle.MhdOracle(3, K, surface=surf, volume=vol)
     s = dgx.MhdSolver(3, K, surface=surf, volume=vol)
@@ -160,10 +160,10 @@ def test_mhd_small_and_large_mesh_kernels(K, vol, surf):
     print(f"K={K} {vol}/{surf}: err {e}", flush=True)
     assert np.all(e <= TOL_FP64), e
     u0 = o.alfven(0.0)
-    ref, tref = o.step(u0, 4, cfl=0.5)
+    ref, tref = o.step(u0, 5, cfl=0.5)
     ud = dev(u0)
     t = torch.zeros(1, dtype=torch.float64, device="cuda")
-    s.step(ud, 4, cfl=0.5, t=t)
+    s.step(ud, 5, cfl=0.5, t=t)
     d = np.abs(host(ud) - ref).max() / np.abs(ref).max()
     assert d <= 1e-12, d
     np.testing.assert_allclose(float(t.item()), tref, rtol=1e-13)
