@@ -342,6 +342,18 @@ __global__ __launch_bounds__(256) void k_stage_curv_split(StageArgs a, Geom g) {
   double um[NV], un[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) um[v] = (a.uin + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
+  // wave 0 runs the epilogue: its RK register and dt are loaded now, their latency hidden
+  // behind the stage (a few blocks leave the chip idle, so registers are not scarce here)
+  double kp[NV], dtp = 0.0;
+  if constexpr (EPI == EPI_RK) {
+    if (w == 0) {
+      dtp = *a.dt;
+      if (a.A != 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) kp[v] = (a.k + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
+      }
+    }
+  }
   if (w < 3) {
     if (a.surf != SURF_NONE) {
       int ec[3];
@@ -421,7 +433,8 @@ __global__ __launch_bounds__(256) void k_stage_curv_split(StageArgs a, Geom g) {
           ls[d] = (fabs(va) + q.c * al) * ij;
         }
         return ok;
-      });
+      },
+      nullptr, EPI == EPI_RK ? kp : nullptr, &dtp);
 }
 
 // Geometry of one element per block (one thread per node): positions from Eq. (2) at the

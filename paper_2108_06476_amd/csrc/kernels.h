@@ -602,7 +602,9 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
                                                const Geom& g, int le, int node, int e, bool inb,
                                                bool active, size_t ENN, size_t own_ix,
                                                const double (&um)[NV], const double (&R)[NV],
-                                               SpeedFn speeds, double* un_out = nullptr) {
+                                               SpeedFn speeds, double* un_out = nullptr,
+                                               const double* kpre = nullptr,
+                                               const double* dtpre = nullptr) {
   using S = Shape<DIM, N, BUDGET>;
   using SS = StageShape<DIM, N, double, BUDGET>;
   constexpr int NN = S::NN;
@@ -614,14 +616,15 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
   } else {
     double un[NV];
     if (active) {
-      const double dt = *a.dt;
+      const double dt = dtpre ? *dtpre : *a.dt;   // kpre, dtpre: loaded by the caller already
       double kv[NV];
       if (a.A == 0.0) {   // first stage: k is not read (uniform branch)
 #pragma unroll
         for (int v = 0; v < NV; ++v) kv[v] = dt * R[v];
       } else {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) kv[v] = a.A * (a.k + (size_t)(own_ix - node) + (size_t)v * ENN)[(unsigned)node] + dt * R[v];
+        for (int v = 0; v < NV; ++v)
+          kv[v] = a.A * (kpre ? kpre[v] : (a.k + (size_t)(own_ix - node) + (size_t)v * ENN)[(unsigned)node]) + dt * R[v];
       }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {

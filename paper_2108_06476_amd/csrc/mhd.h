@@ -489,6 +489,18 @@ __global__ __launch_bounds__(192) void k_stage_mhd_split(StageArgs a, Geom g) {
   double um[8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) um[v] = (a.uin + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
+  // wave 0 runs the epilogue: its RK register and dt are loaded now, their latency hidden
+  // behind the stage (a few blocks leave the chip idle, so registers are not scarce here)
+  double kp[8], dtp = 0.0;
+  if constexpr (EPI == EPI_RK) {
+    if (w == 0) {
+      dtp = *a.dt;
+      if (a.A != 0.0) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) kp[v] = (a.k + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
+      }
+    }
+  }
   MhdPrim qm;
   if (!mhd_prim(um, g.gamma, qm)) *g.flag = 1;
   int ec[3];
@@ -555,7 +567,8 @@ __global__ __launch_bounds__(192) void k_stage_mhd_split(StageArgs a, Geom g) {
         ls[1] = sT[TAB_JAC + 1] * (fabs(q.v[1]) + mhd_cf<1>(q));
         ls[2] = sT[TAB_JAC + 2] * (fabs(q.v[2]) + mhd_cf<2>(q));
         return ok;
-      });
+      },
+      nullptr, EPI == EPI_RK ? kp : nullptr, &dtp);
 }
 
 template <int N>
