@@ -368,11 +368,22 @@ bool shock_steps(dgx_handle h) {
   return h->cfg.volume == DGX_VOL_SHOCKCAP_HG && !h->curved && !h->mhd;
 }
 
+// Curvilinear and MHD handles whose stages run several waves per element (N = 3, few
+// elements): there the first stage of an adaptive step derives dt itself (one launch fewer
+// per step on a latency-bound mesh), with the same value and time updates as k_dt_final.
+static bool stage_derives_dt(dgx_handle h) {
+  return h->N == 3 && ((h->curved && h->E <= CURV_SPLIT_MAX_E) ||
+                       (h->mhd && h->E <= MHD_SPLIT_MAX_E));
+}
+
 dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double cfl,
                         double dt_fixed, double* t, bool emit, bool fresh, int j0) {
   const bool adaptive = cfl > 0.0;
   double* t0 = h->g.source ? h->t0 : nullptr;   // step start time for the stage times
-  if (adaptive) {
+  const bool in_stage = adaptive && stage_derives_dt(h);
+  if (in_stage) {
+    // dt from the partials in the first stage, the time advanced by the second
+  } else if (adaptive) {
     launch_dt_final(h->stream, h->partial, h->npart, cfl, (double)(h->N + 1), h->dt, t, t0);
   } else {
     hipLaunchKernelGGL(k_set_dt, dim3(1), dim3(64), 0, h->stream, dt_fixed, h->dt, t, t0);
@@ -405,6 +416,20 @@ dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double 
     a.speed = (adaptive && st == 4 && emit) ? h->partial : nullptr;
     a.t0 = t0;
     a.cs = CK_C[st];
+    if (in_stage && st == 0) {   // c_1 = 0: the source time is the step's start, t itself
+      a.dt_from = h->partial;
+      a.dt_np = h->npart;
+      a.dt_cfl = cfl;
+      a.dt_n1 = (double)(h->N + 1);
+      a.dt_pub = h->dt;
+      a.t_cur = t;
+      a.t0_pub = t0;
+      a.t0 = t0 ? t : nullptr;
+      a.t_step = 1;
+    } else if (in_stage && st == 1) {
+      a.t_cur = t;
+      a.t_step = 2;
+    }
     a.kw = st < 4;
     // the stages of one step run back to back (an indicator kernel only precedes stage 0)
     HIPCHK(h, launch_stage(h, a, EPI_RK, st == 4));

@@ -274,7 +274,7 @@ __device__ __forceinline__ void stage_tile_curv(typename CurvLdsOf<N, VOL>::type
 #pragma unroll
     for (int v = 0; v < NV; ++v) R[v] *= ij;
     if (g.source) {
-      const double ts = a.t0 ? *a.t0 + a.cs * *a.dt : a.t;
+      const double ts = a.t0 ? (a.cs == 0.0 ? *a.t0 : *a.t0 + a.cs * *a.dt) : a.t;
       double src[NV];
       mms_source(g.gamma, g.xyz[own_ix], g.xyz[ENN + own_ix], g.xyz[2 * ENN + own_ix], ts, src);
 #pragma unroll
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(256) void k_stage_curv_split(StageArgs a, Geom g) {
   double kp[NV], dtp = 0.0;
   if constexpr (EPI == EPI_RK) {
     if (w == 0) {
-      dtp = *a.dt;
+      dtp = a.dt_from ? stage_dt_from_partials(a) : *a.dt;
       if (a.A != 0.0) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) kp[v] = (a.k + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
@@ -404,7 +404,7 @@ __global__ __launch_bounds__(256) void k_stage_curv_split(StageArgs a, Geom g) {
   if (w == 1) {
     double src[NV] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (g.source) {
-      const double ts = a.t0 ? *a.t0 + a.cs * *a.dt : a.t;
+      const double ts = a.t0 ? (a.cs == 0.0 ? *a.t0 : *a.t0 + a.cs * *a.dt) : a.t;
       mms_source(g.gamma, g.xyz[own_ix], g.xyz[ENN + own_ix], g.xyz[2 * ENN + own_ix], ts, src);
     }
 #pragma unroll
@@ -435,6 +435,9 @@ __global__ __launch_bounds__(256) void k_stage_curv_split(StageArgs a, Geom g) {
         return ok;
       },
       nullptr, EPI == EPI_RK ? kp : nullptr, &dtp);
+  if constexpr (EPI == EPI_RK) {
+    if (a.t_step && blockIdx.x == 0 && node == 0) stage_time_publish(a, dtp);
+  }
 }
 
 // Geometry of one element per block (one thread per node): positions from Eq. (2) at the

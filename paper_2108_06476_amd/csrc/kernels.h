@@ -512,7 +512,46 @@ struct StageArgs {
   // smoothed factors); each element then smooths its own from it and its face neighbours'
   const double* alpha_raw_in = nullptr;
   int alpha_smooth = 0;
+  // small meshes (several waves per element): the first stage of an adaptive step derives dt
+  // itself from the per-element wave-speed partials dt_from[0, dt_np) (every block alike,
+  // dt = dt_cfl 2 / (dt_n1 max)); block 0 publishes it to dt_pub and the step's start time
+  // *t_cur to t0_pub (if set).  t_step = 2 marks the second stage, whose block 0 advances
+  // *t_cur by the step's dt (nothing reads t_cur while a step runs).
+  const double* dt_from = nullptr;
+  int64_t dt_np = 0;
+  double dt_cfl = 0.0, dt_n1 = 0.0;
+  double* dt_pub = nullptr;
+  double* t_cur = nullptr;
+  double* t0_pub = nullptr;
+  int t_step = 0;
 };
+
+// The first-stage dt of StageArgs::dt_from, reduced by one wave (all 64 lanes active): the
+// same value as k_dt_final's (max is exact), in every lane.
+__device__ __forceinline__ double stage_dt_from_partials(const StageArgs& a) {
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t i = threadIdx.x & 63u;
+  for (; i + 3 * 64 < a.dt_np; i += 4 * 64) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m[k] = fmax(m[k], a.dt_from[i + k * 64]);
+  }
+  for (; i < a.dt_np; i += 64) m[0] = fmax(m[0], a.dt_from[i]);
+  const double r = wave_max_lane63(fmax(fmax(m[0], m[1]), fmax(m[2], m[3])));
+  const double mx = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(r), 63),
+                                     __builtin_amdgcn_readlane(__double2loint(r), 63));
+  return a.dt_cfl * 2.0 / (a.dt_n1 * mx);
+}
+
+// Block 0's part of StageArgs::t_step (called by one thread after the stage's own reads of
+// dt and t): stage 1 publishes dt and the step's start time, stage 2 advances t.
+__device__ __forceinline__ void stage_time_publish(const StageArgs& a, double dt_stage1) {
+  if (a.t_step == 1) {
+    *a.dt_pub = dt_stage1;
+    if (a.t0_pub && a.t_cur) *a.t0_pub = *a.t_cur;
+  } else if (a.t_step == 2 && a.t_cur) {
+    *a.t_cur += *a.dt;
+  }
+}
 
 // Weak form: the physical fluxes f^d_v of every node, contracted along the lines.
 template <int DIM, int NE_NN, int XB>

@@ -494,7 +494,7 @@ __global__ __launch_bounds__(192) void k_stage_mhd_split(StageArgs a, Geom g) {
   double kp[8], dtp = 0.0;
   if constexpr (EPI == EPI_RK) {
     if (w == 0) {
-      dtp = *a.dt;
+      dtp = a.dt_from ? stage_dt_from_partials(a) : *a.dt;
       if (a.A != 0.0) {
 #pragma unroll
         for (int v = 0; v < 8; ++v) kp[v] = (a.k + (size_t)e * NN + (size_t)v * ENN)[(unsigned)node];
@@ -569,6 +569,9 @@ __global__ __launch_bounds__(192) void k_stage_mhd_split(StageArgs a, Geom g) {
         return ok;
       },
       nullptr, EPI == EPI_RK ? kp : nullptr, &dtp);
+  if constexpr (EPI == EPI_RK) {
+    if (a.t_step && blockIdx.x == 0 && node == 0) stage_time_publish(a, dtp);
+  }
 }
 
 template <int N>
