@@ -368,12 +368,17 @@ bool shock_steps(dgx_handle h) {
   return h->cfg.volume == DGX_VOL_SHOCKCAP_HG && !h->curved && !h->mhd;
 }
 
-// Curvilinear and MHD handles whose stages run several waves per element (N = 3, few
-// elements): there the first stage of an adaptive step derives dt itself (one launch fewer
-// per step on a latency-bound mesh), with the same value and time updates as k_dt_final.
+// Small meshes (at most STAGE_DT_MAX_E elements; for curvilinear and MHD handles those whose
+// N = 3 stages run several waves per element): the first stage of an adaptive step derives
+// dt itself, every wave reducing the partials (one launch fewer per step on a latency-bound
+// mesh), with the same value and time updates as k_dt_final.
+constexpr int64_t STAGE_DT_MAX_E = 512;
+
 static bool stage_derives_dt(dgx_handle h) {
-  return h->N == 3 && ((h->curved && h->E <= CURV_SPLIT_MAX_E) ||
-                       (h->mhd && h->E <= MHD_SPLIT_MAX_E));
+  if (h->E > STAGE_DT_MAX_E) return false;
+  if (h->curved) return h->N == 3 && h->E <= CURV_SPLIT_MAX_E;
+  if (h->mhd) return h->N == 3 && h->E <= MHD_SPLIT_MAX_E;
+  return true;
 }
 
 dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double cfl,

@@ -434,7 +434,7 @@ __global__ __launch_bounds__(256) void k_stage_curv_split(StageArgs a, Geom g) {
         }
         return ok;
       },
-      nullptr, EPI == EPI_RK ? kp : nullptr, &dtp);
+      nullptr, EPI == EPI_RK ? kp : nullptr, dtp);
   if constexpr (EPI == EPI_RK) {
     if (a.t_step && blockIdx.x == 0 && node == 0) stage_time_publish(a, dtp);
   }

@@ -636,17 +636,19 @@ __device__ __forceinline__ void weak_dir(const L& s, int base, int node, const d
 // sum_d max_nodes lam_d of the new state: speeds(u_new, lam) gives the directions' scaled
 // wave speeds and returns false for a non-physical state.
 // xb: the block's per-element LDS slots (elements of several waves reduce through them).
-template <int DIM, int N, int NV, int EPI, int BUDGET, typename SpeedFn>
-__device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArgs& a,
+// DTF: the caller may ask (a.dt_from) for the first stage's dt to be derived here.
+template <int DIM, int N, int NV, int EPI, int BUDGET, typename SpeedFn, bool DTF = false>
+__device__ __forceinline__ double stage_epilogue(unsigned char* xb, const StageArgs& a,
                                                const Geom& g, int le, int node, int e, bool inb,
                                                bool active, size_t ENN, size_t own_ix,
                                                const double (&um)[NV], const double (&R)[NV],
                                                SpeedFn speeds, double* un_out = nullptr,
                                                const double* kpre = nullptr,
-                                               const double* dtpre = nullptr) {
+                                               double dtpre = 0.0) {
   using S = Shape<DIM, N, BUDGET>;
   using SS = StageShape<DIM, N, double, BUDGET>;
   constexpr int NN = S::NN;
+  double dt_used = 0.0;
   if constexpr (EPI == EPI_RHS) {
     if (active) {
 #pragma unroll
@@ -654,8 +656,16 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
     }
   } else {
     double un[NV];
+    // dtpre (> 0): dt loaded or derived by the caller; a first stage that derives dt itself
+    // (a.dt_from) reduces the partials here, where few registers are live (every lane of
+    // the wave reaches this point)
+    if (dtpre > 0.0) dt_used = dtpre;
+    else if constexpr (DTF) {
+      if (a.dt_from) dt_used = stage_dt_from_partials(a);
+    }
     if (active) {
-      const double dt = dtpre ? *dtpre : *a.dt;   // kpre, dtpre: loaded by the caller already
+      // kpre: the RK register loaded by the caller already
+      const double dt = dt_used > 0.0 ? dt_used : *a.dt;
       double kv[NV];
       if (a.A == 0.0) {   // first stage: k is not read (uniform branch)
 #pragma unroll
@@ -717,6 +727,7 @@ __device__ __forceinline__ void stage_epilogue(unsigned char* xb, const StageArg
       }
     }
   }
+  return dt_used;
 }
 
 // The indicator of one element from q = rho p at its nodes: w0, w1, w2 are NN-double LDS
@@ -1013,16 +1024,15 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   // ---- epilogue
   constexpr bool IND = VOL == VOL_SHOCKCAP && EPI == EPI_RK;   // indicator of the output
   double un[NV];
-  stage_epilogue<DIM, N, NV, EPI, BUDGET>(
-      s.xb, a, g, le, node, e, inb, active, ENN, own_ix, um, R,
-      [&](const double (&un)[NV], double (&ls)[DIM]) {
+  auto speeds = [&](const double (&un)[NV], double (&ls)[DIM]) {
         Prim<double> q;
         const bool ok = cons_to_prim<DIM, false>(un, g.gamma, q);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) ls[d] = sT[TAB_JAC + d] * (fabs(q.v[d]) + q.c);
         return ok;
-      },
-      IND ? un : nullptr);
+      };
+  const double dt_used = stage_epilogue<DIM, N, NV, EPI, BUDGET, decltype(speeds), true>(
+      s.xb, a, g, le, node, e, inb, active, ENN, own_ix, um, R, speeds, IND ? un : nullptr);
   // shock capturing: the raw indicator of the state just written, for the next stage (the
   // computation of k_indicator on the same values, in the element's LDS slot)
   if constexpr (IND) {
@@ -1038,6 +1048,9 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
                              a.ind_sharp, a.ind_amin, a.ind_amax, a.ind_xcut, a.alpha_next,
                              nullptr, e);
     }
+  }
+  if constexpr (EPI == EPI_RK) {
+    if (a.t_step && blockIdx.x == 0 && threadIdx.x == 0) stage_time_publish(a, dt_used);
   }
 }
 

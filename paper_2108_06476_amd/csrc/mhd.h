@@ -568,7 +568,7 @@ __global__ __launch_bounds__(192) void k_stage_mhd_split(StageArgs a, Geom g) {
         ls[2] = sT[TAB_JAC + 2] * (fabs(q.v[2]) + mhd_cf<2>(q));
         return ok;
       },
-      nullptr, EPI == EPI_RK ? kp : nullptr, &dtp);
+      nullptr, EPI == EPI_RK ? kp : nullptr, dtp);
   if constexpr (EPI == EPI_RK) {
     if (a.t_step && blockIdx.x == 0 && node == 0) stage_time_publish(a, dtp);
   }
