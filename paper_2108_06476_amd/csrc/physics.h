@@ -48,12 +48,32 @@ __device__ __forceinline__ double sqrt_pos(double x) {
   return fma(d, h, g);
 }
 
-// artanh(z)/z = sum_k z^(2k)/(2k+1), k = 0..15: below z^2 = 0.1 the truncation is under
-// 3.3e-18 relative (the first omitted term z^32/33 over 1 - z^2).
-__device__ __forceinline__ double artanh_over_z(double z2) {
-  double p = 1.0 / 31.0;
+// The log means' middle branch (1e-4 <= z^2 < 0.1) as polynomials of degree 10 in x = z^2:
+// P(x) = z/(2 artanh z) and 2Q(x) = 2 artanh(z)/z, the interpolants at Chebyshev nodes of
+// [0, 0.1] formed at 60 digits (logmean_fit.py beside this file).  Both are analytic for
+// |x| < 1, so ten degrees leave about 1e-18 relative error with these float64 coefficients,
+// and neither needs a reciprocal or a logarithm.
+__device__ __forceinline__ double ln_mean_mid(double x) {
+  constexpr double kP[11] = {
+      0.5, -0.1666666666666666, -0.04444444444447207, -0.023280423276128673,
+      -0.015097002105376345, -0.010898386189257736, -0.008394230906424155,
+      -0.00674302519561495, -0.005699575913500763, -0.004061649743847389,
+      -0.006793753103187953};
+  double p = kP[10];
 #pragma unroll
-  for (int k = 14; k >= 0; --k) p = fma(p, z2, 1.0 / (2 * k + 1));
+  for (int k = 9; k >= 0; --k) p = fma(p, x, kP[k]);
+  return p;
+}
+
+__device__ __forceinline__ double inv_ln_mean_mid(double x) {
+  constexpr double kQ[11] = {   // Q(x) = artanh(z)/z; the factor 2 is applied exactly below
+      1.0, 0.3333333333333325, 0.20000000000033863, 0.14285714280450776,
+      0.11111111529834054, 0.09090889710268459, 0.07692864848122398,
+      0.06656438300891282, 0.060018248406360414, 0.04412879698538037,
+      0.0802184520988054};
+  double p = 2.0 * kQ[10];
+#pragma unroll
+  for (int k = 9; k >= 0; --k) p = fma(p, x, 2.0 * kQ[k]);
   return p;
 }
 
@@ -62,7 +82,7 @@ __device__ __forceinline__ double artanh_over_z(double z2) {
 // 1/{{a}}_ln = 2/(a + b) * artanh(z)/z.  Below z^2 = 1e-4 (the threshold of the efficiency
 // reference the paper cites, Section 3.2) both use their Taylor series in z^2 to z^6
 // (truncation below 1.2e-17), so one reciprocal of a + b serves the whole evaluation; up to
-// z^2 = 0.1 (states within a factor 1.9) the 16-term series of artanh(z)/z replaces the
+// z^2 = 0.1 (states within a factor 1.9) the degree-10 polynomials above replace the
 // logarithm and its two divisions (MID; a kernel that never meets such jumps and is short of
 // registers leaves it out); beyond it the logarithm.
 template <bool MID = true>
@@ -72,7 +92,7 @@ __device__ __forceinline__ double ln_mean(double a, double b) {
   const double z = d * r, z2 = z * z;
   if (z2 < 1.0e-4)   // (s/2)(1 - z^2/3 - 4 z^4/45 - 44 z^6/945), the 1/2 in the coefficients
     return s * (0.5 + z2 * (-1.0 / 6.0 + z2 * (-2.0 / 45.0 + z2 * (-22.0 / 945.0))));
-  if (MID && z2 < 0.1) return 0.5 * s * rcp_nr(artanh_over_z(z2));
+  if (MID && z2 < 0.1) return s * ln_mean_mid(z2);
   const double hi = fmax(a, b), lo = fmin(a, b);   // symmetric in (a, b), bit for bit
   return (hi - lo) / log(hi / lo);
 }
@@ -86,7 +106,7 @@ __device__ __forceinline__ double inv_ln_mean(double a, double b) {
   const double z = d * r, z2 = z * z;
   if (z2 < 1.0e-4)   // (2/s)(1 + z^2/3 + z^4/5 + z^6/7), the 2 in the coefficients
     return r * (2.0 + z2 * (2.0 / 3.0 + z2 * (2.0 / 5.0 + z2 * (2.0 / 7.0))));
-  if (MID && z2 < 0.1) return 2.0 * r * artanh_over_z(z2);
+  if (MID && z2 < 0.1) return r * inv_ln_mean_mid(z2);
   const double hi = fmax(a, b), lo = fmin(a, b);
   return log(hi / lo) / (hi - lo);
 }
