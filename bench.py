@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--precision", default=None, help="override the main line's precision")
     ap.add_argument("--warmup-floor", type=float, default=WARMUP_FLOOR_S,
                     help="seconds of warm-up at least (0 under a profiler)")
+    ap.add_argument("--ensemble-shape", default=None, metavar="BLOCK,GRID",
+                    help="fix the ensemble's tile instead of tuning it (e.g. 512,0)")
     ap.add_argument("--rhs-only", action="store_true",
                     help="profiling: time --steps right-hand-side evaluations (dgx_rhs) of the "
                          "main line's configuration instead of RK steps, and stop there (for "
@@ -397,7 +399,10 @@ def bench_batched(args, precision="fp64"):
         total += o.num_nodes
         o.close()
     t0 = time.perf_counter()
-    shape = b.tune(us, budget_ms=3000)
+    if args.ensemble_shape:   # fixed tile (counter runs compare one kernel across passes)
+        shape = b.set_shape(*(int(v) for v in args.ensemble_shape.split(",")))
+    else:
+        shape = b.tune(us, budget_ms=3000)
     tune_s = time.perf_counter() - t0
     run = lambda n: b.step(us, n, cfl=0.5)
     warm_up(run, 2)
