@@ -120,6 +120,17 @@ static void launch_dt_final(hipStream_t st, const double* partial, int64_t np, d
     hipLaunchKernelGGL(k_dt_final<1024>, dim3(1), dim3(1024), 0, st, partial, np, cfl, n1, dt, t, t0);
 }
 
+// The start of a dgx_step call on a mesh whose stages keep the wave speeds in slots: the
+// max of k_maxspeed's per-element partials into slot 0, the other slots cleared; the first
+// stage then takes dt from the slots as in every later step.
+__global__ __launch_bounds__(1024) void k_dt_seed(const double* __restrict__ partial, int64_t np,
+                                                  double* __restrict__ slots) {
+  __shared__ double s[16];
+  const double m = block_max<1024>(partial, np, s);
+  if (threadIdx.x == 0) slots[0] = m;
+  else if (threadIdx.x < (unsigned)DT_SLOTS) slots[threadIdx.x * DT_SLOT_STRIDE] = 0.0;
+}
+
 __global__ void k_set_dt(double v, double* __restrict__ dt, double* __restrict__ t,
                          double* __restrict__ t0) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -204,6 +215,7 @@ struct dgx_solver {
   double* energy = nullptr;
   double* partial = nullptr;
   int64_t npart = 0;   // wave-speed partials (one per element)
+  double* slots = nullptr;   // DT_SLOTS wave-speed maxima, DT_SLOT_STRIDE doubles apart
   int64_t nblk = 0;    // blocks of the element-tiled kernels (integral partials)
   double* dt = nullptr;
   int* flag = nullptr;
@@ -358,8 +370,9 @@ dgx_status enqueue_rhs(dgx_handle h, const double* u, double* du, const double* 
 }
 
 
-// One RK step on h->stream: dt (adaptive: from the partials in h->partial), then the five
-// stages; emit: the last stage writes the next step's partials.  cur: which of buf holds
+// One RK step on h->stream: dt (adaptive: from the partials in h->partial, or, see
+// stage_slots, from the slots in h->slots), then the five stages; emit: the last stage writes
+// the next step's partials (or folds them into the slots).  cur: which of buf holds
 // the state (toggled by every stage).  Shock capturing: every stage writes the raw
 // indicator of its output state and smooths its input's itself; the first stage of a step
 // with fresh set (the first of a call) has it computed first.  j0: the parity of the
@@ -381,11 +394,23 @@ static bool stage_derives_dt(dgx_handle h) {
   return true;
 }
 
+// Mid-size Cartesian meshes: the last stage of a step folds the element wave speeds into
+// DT_SLOTS slots by atomic max, and the next step's first stage derives dt from those
+// (every wave reducing 64 values): no dt kernel between the steps.  From STAGE_SLOTS_MAX_E
+// elements on, the 6 us that k_dt_final takes are a small part of a step and the atomics
+// and slot reads cost about as much, so those meshes keep k_dt_final.
+constexpr int64_t STAGE_SLOTS_MAX_E = 16384;
+
+static bool stage_slots(dgx_handle h) {
+  return !h->curved && !h->mhd && h->E > STAGE_DT_MAX_E && h->E < STAGE_SLOTS_MAX_E;
+}
+
 dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double cfl,
                         double dt_fixed, double* t, bool emit, bool fresh, int j0) {
   const bool adaptive = cfl > 0.0;
   double* t0 = h->g.source ? h->t0 : nullptr;   // step start time for the stage times
-  const bool in_stage = adaptive && stage_derives_dt(h);
+  const bool slots = adaptive && stage_slots(h);
+  const bool in_stage = adaptive && (stage_derives_dt(h) || slots);
   if (in_stage) {
     // dt from the partials in the first stage, the time advanced by the second
   } else if (adaptive) {
@@ -418,12 +443,14 @@ dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double 
     a.uout = buf[1 - cur];
     a.A = CK_A[st];
     a.B = CK_B[st];
-    a.speed = (adaptive && st == 4 && emit) ? h->partial : nullptr;
+    a.speed = (adaptive && st == 4 && emit && !slots) ? h->partial : nullptr;
+    a.speed_slots = (st == 4 && emit && slots) ? h->slots : nullptr;
     a.t0 = t0;
     a.cs = CK_C[st];
     if (in_stage && st == 0) {   // c_1 = 0: the source time is the step's start, t itself
-      a.dt_from = h->partial;
-      a.dt_np = h->npart;
+      a.dt_from = slots ? h->slots : h->partial;
+      a.dt_np = slots ? DT_SLOTS : h->npart;
+      a.dt_stride = slots ? DT_SLOT_STRIDE : 1;
       a.dt_cfl = cfl;
       a.dt_n1 = (double)(h->N + 1);
       a.dt_pub = h->dt;
@@ -434,6 +461,7 @@ dgx_status enqueue_step(dgx_handle h, double* const (&buf)[2], int& cur, double 
     } else if (in_stage && st == 1) {
       a.t_cur = t;
       a.t_step = 2;
+      if (slots) a.slots_clear = h->slots;   // read by stage 0, written again by stage 4
     }
     a.kw = st < 4;
     // the stages of one step run back to back (an indicator kernel only precedes stage 0)
@@ -595,12 +623,14 @@ dgx_status create_impl(const dgx_config& c, const dgx_curv_config* cv, void* hip
             alloc((void**)&h->alpha_raw, sizeof(double) * h->E) &&
             alloc((void**)&h->energy, sizeof(double) * h->E) &&
             alloc((void**)&h->partial, sizeof(double) * std::max<size_t>(7 * (size_t)nblk, (size_t)h->E)) &&
-            alloc((void**)&h->dt, sizeof(double) * 2) && alloc((void**)&h->flag, sizeof(int) * 2);
+            alloc((void**)&h->dt, sizeof(double) * 2) && alloc((void**)&h->flag, sizeof(int) * 2) &&
+            alloc((void**)&h->slots, sizeof(double) * DT_SLOTS * DT_SLOT_STRIDE);
   if (!ok) {
     dgx_destroy(h);
     return DGX_ENOMEM;
   }
   if (hipMemcpy(h->tab, T.data(), sizeof(double) * TAB_SIZE, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(h->slots, 0, sizeof(double) * DT_SLOTS * DT_SLOT_STRIDE) != hipSuccess ||
       hipMemset(h->k, 0, state_bytes(h)) != hipSuccess ||
       hipMemset(h->alpha, 0, sizeof(double) * h->E) != hipSuccess ||
       hipMemset(h->flag, 0, sizeof(int) * 2) != hipSuccess ||
@@ -724,7 +754,7 @@ dgx_status dgx_destroy(dgx_handle h) {
   else (void)hipDeviceSynchronize();
   for (void* p : {(void*)h->tab, (void*)h->u2, (void*)h->k, (void*)h->alpha, (void*)h->alpha_raw,
                   (void*)h->energy, (void*)h->partial, (void*)h->dt, (void*)h->flag, (void*)h->ja,
-                  (void*)h->jac, (void*)h->xyz, (void*)h->dmat, (void*)h->t0})
+                  (void*)h->jac, (void*)h->xyz, (void*)h->dmat, (void*)h->t0, (void*)h->slots})
     if (p) (void)hipFree(p);
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
   drop_step_graph(h);
@@ -834,7 +864,13 @@ dgx_status dgx_step(dgx_handle h, double* u, int32_t nsteps, double cfl, double 
   // neighbours' face states of its input while other blocks write their output
   double* buf[2] = {u, h->u2};
   int cur = 0;
-  if (adaptive) HIPCHK(h, enqueue_maxspeed(h, u));
+  if (adaptive) {
+    HIPCHK(h, enqueue_maxspeed(h, u));
+    if (stage_slots(h)) {
+      hipLaunchKernelGGL(k_dt_seed, dim3(1), dim3(1024), 0, h->stream, h->partial, h->npart, h->slots);
+      HIPCHK(h, hipGetLastError());
+    }
+  }
   int s = 0;
   if (nsteps >= 2 && !h->prof) {
     // pairs of steps from the captured graph (ten stages: the state is back in u)

@@ -519,6 +519,13 @@ struct StageArgs {
   // *t_cur by the step's dt (nothing reads t_cur while a step runs).
   const double* dt_from = nullptr;
   int64_t dt_np = 0;
+  int64_t dt_stride = 1;   // dt_from holds its values dt_stride doubles apart
+  // Large meshes: the last stage folds each element's wave speed into the DT_SLOTS slots
+  // of speed_slots (an atomic max on the bits of a positive double, slot e % DT_SLOTS), the
+  // next step's first stage reduces them (dt_from, dt_np = DT_SLOTS, dt_stride =
+  // DT_SLOT_STRIDE), and block 0 of its second stage clears them (slots_clear).
+  double* speed_slots = nullptr;
+  double* slots_clear = nullptr;
   double dt_cfl = 0.0, dt_n1 = 0.0;
   double* dt_pub = nullptr;
   double* t_cur = nullptr;
@@ -526,16 +533,32 @@ struct StageArgs {
   int t_step = 0;
 };
 
+// The wave-speed slots of StageArgs::speed_slots: DT_SLOTS maxima, DT_SLOT_STRIDE doubles
+// (512 B) apart so that the atomics of different slots spread over the memory channels.
+constexpr int DT_SLOTS = 64;
+constexpr int DT_SLOT_STRIDE = 64;
+
+// One element's wave speed into its slot.  Non-negative doubles order as their bit patterns
+// do, so an unsigned 64-bit atomic max keeps the exact maximum whatever the order; zero and
+// NaN are skipped, as the fmax reductions of the partials skip NaN.
+__device__ __forceinline__ void slot_max(double* slots, int e, double lam) {
+  if (lam > 0.0)
+    __hip_atomic_fetch_max(
+        reinterpret_cast<unsigned long long*>(slots + (size_t)(e & (DT_SLOTS - 1)) * DT_SLOT_STRIDE),
+        (unsigned long long)__double_as_longlong(lam), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The first-stage dt of StageArgs::dt_from, reduced by one wave (all 64 lanes active): the
 // same value as k_dt_final's (max is exact), in every lane.
 __device__ __forceinline__ double stage_dt_from_partials(const StageArgs& a) {
   double m[4] = {0.0, 0.0, 0.0, 0.0};
   int64_t i = threadIdx.x & 63u;
+  const int64_t sd = a.dt_stride;
   for (; i + 3 * 64 < a.dt_np; i += 4 * 64) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) m[k] = fmax(m[k], a.dt_from[i + k * 64]);
+    for (int k = 0; k < 4; ++k) m[k] = fmax(m[k], a.dt_from[(i + k * 64) * sd]);
   }
-  for (; i < a.dt_np; i += 64) m[0] = fmax(m[0], a.dt_from[i]);
+  for (; i < a.dt_np; i += 64) m[0] = fmax(m[0], a.dt_from[i * sd]);
   const double r = wave_max_lane63(fmax(fmax(m[0], m[1]), fmax(m[2], m[3])));
   const double mx = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(r), 63),
                                      __builtin_amdgcn_readlane(__double2loint(r), 63));
@@ -636,7 +659,8 @@ __device__ __forceinline__ void weak_dir(const L& s, int base, int node, const d
 // sum_d max_nodes lam_d of the new state: speeds(u_new, lam) gives the directions' scaled
 // wave speeds and returns false for a non-physical state.
 // xb: the block's per-element LDS slots (elements of several waves reduce through them).
-// DTF: the caller may ask (a.dt_from) for the first stage's dt to be derived here.
+// DTF: the caller may ask for the first stage's dt to be derived here (a.dt_from) and for
+// the last stage's wave speeds to be folded into slots (a.speed_slots).
 template <int DIM, int N, int NV, int EPI, int BUDGET, typename SpeedFn, bool DTF = false>
 __device__ __forceinline__ double stage_epilogue(unsigned char* xb, const StageArgs& a,
                                                const Geom& g, int le, int node, int e, bool inb,
@@ -684,7 +708,8 @@ __device__ __forceinline__ double stage_epilogue(unsigned char* xb, const StageA
         if (un_out) un_out[v] = un[v];
       }
     }
-    if (a.speed != nullptr) {
+    double* const slots = DTF ? a.speed_slots : nullptr;
+    if (a.speed != nullptr || slots != nullptr) {
       if constexpr (WaveElem<DIM, N>::value) {
         if (active) {   // uniform per wave: the element is the wave
           double ls[DIM];
@@ -692,7 +717,10 @@ __device__ __forceinline__ double stage_epilogue(unsigned char* xb, const StageA
           double lam = 0.0;
 #pragma unroll
           for (int d = 0; d < DIM; ++d) lam += wave_max_lane63(ls[d]);
-          if (node == NN - 1) a.speed[e] = lam;
+          if (node == NN - 1) {
+            if (DTF && slots) slot_max(slots, e, lam);
+            else a.speed[e] = lam;
+          }
         }
       } else {
         constexpr int P2 = NN <= 4 ? 4 : NN <= 16 ? 16 : NN <= 64 ? 64 : NN <= 128 ? 128 : NN <= 256 ? 256 : 512;
@@ -722,7 +750,8 @@ __device__ __forceinline__ double stage_epilogue(unsigned char* xb, const StageA
           double lam = 0.0;
 #pragma unroll
           for (int d = 0; d < DIM; ++d) lam += sp[d * NN];
-          a.speed[e] = lam;
+          if (DTF && slots) slot_max(slots, e, lam);
+          else a.speed[e] = lam;
         }
       }
     }
@@ -1051,6 +1080,8 @@ __device__ __forceinline__ void stage_tile(typename StageLdsOf<DIM, N, VOL, RT, 
   }
   if constexpr (EPI == EPI_RK) {
     if (a.t_step && blockIdx.x == 0 && threadIdx.x == 0) stage_time_publish(a, dt_used);
+    if (a.slots_clear && blockIdx.x == 0 && threadIdx.x < (unsigned)DT_SLOTS)
+      a.slots_clear[threadIdx.x * DT_SLOT_STRIDE] = 0.0;
   }
 }
 

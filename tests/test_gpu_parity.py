@@ -258,6 +258,32 @@ def test_sedov_steps_parity_small(nsteps):
     np.testing.assert_allclose(host(t)[0], tref, rtol=1e-13)
 
 
+@pytest.mark.parametrize("name", ["tgv_32", "sedov_32"])
+def test_steps_above_the_small_mesh_limit(name):
+    """Above 512 elements each step's last stage folds the element wave speeds into 64 slots
+    by atomic max and the next step's first stage takes dt from them (a call's first step
+    from k_maxspeed's partials): 5 steps in one call and in calls of 1, 2 and 2 steps, each
+    against the oracle per field at 1e-12 and in t at 1e-13."""
+    cfg = inputs.scaled(inputs.workload(name), cells=(9, 8, 8))
+    o = oracle.Oracle(**cfg)
+    s = dgx.Solver(**cfg)
+    xyz = o.node_coords()
+    u0 = inputs.tgv(xyz) if name == "tgv_32" else inputs.sedov(xyz)
+    for calls in ((5,), (1, 2, 2)):
+        ud = dev(u0)
+        t = torch.zeros(1, dtype=torch.float64, device="cuda")
+        done = 0
+        for n in calls:
+            s.step(ud, n, cfl=0.5, t=t)
+            done += n
+        ref, tref = o.step(u0, done, cfl=0.5)
+        assert s.check() == 0
+        d = state_err(host(ud), ref, 3)
+        _say(name, calls, "state err", d, "t", host(t)[0], tref)
+        assert np.all(d <= 1e-12), (calls, d)
+        np.testing.assert_allclose(host(t)[0], tref, rtol=1e-13)
+
+
 def test_determinism():
     cfg = _cfg(3, 3, (4, 4, 4), "ec", "llf")
     o = oracle.Oracle(**cfg)
