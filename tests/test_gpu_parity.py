@@ -258,17 +258,22 @@ def test_sedov_steps_parity_small(nsteps):
     np.testing.assert_allclose(host(t)[0], tref, rtol=1e-13)
 
 
-@pytest.mark.parametrize("name", ["tgv_32", "sedov_32"])
-def test_steps_above_the_small_mesh_limit(name):
+@pytest.mark.parametrize("name,cells,polydeg", [
+    ("tgv_32", (9, 8, 8), 3), ("sedov_32", (9, 8, 8), 3),     # one wave per element
+    ("tgv_32", (9, 8, 8), 4),                                  # 125 nodes: block reductions
+    ("density_wave_2d", (24, 24), 3)])                         # 16 elements per block
+def test_steps_above_the_small_mesh_limit(name, cells, polydeg):
     """Above 512 elements each step's last stage folds the element wave speeds into 64 slots
     by atomic max and the next step's first stage takes dt from them (a call's first step
     from k_maxspeed's partials): 5 steps in one call and in calls of 1, 2 and 2 steps, each
     against the oracle per field at 1e-12 and in t at 1e-13."""
-    cfg = inputs.scaled(inputs.workload(name), cells=(9, 8, 8))
+    cfg = inputs.scaled(inputs.workload(name), cells=cells, polydeg=polydeg)
+    dim = cfg["dim"]
     o = oracle.Oracle(**cfg)
     s = dgx.Solver(**cfg)
     xyz = o.node_coords()
-    u0 = inputs.tgv(xyz) if name == "tgv_32" else inputs.sedov(xyz)
+    u0 = (inputs.tgv(xyz) if name == "tgv_32" else inputs.sedov(xyz) if name == "sedov_32"
+          else inputs.density_wave(xyz))
     for calls in ((5,), (1, 2, 2)):
         ud = dev(u0)
         t = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -278,8 +283,8 @@ def test_steps_above_the_small_mesh_limit(name):
             done += n
         ref, tref = o.step(u0, done, cfl=0.5)
         assert s.check() == 0
-        d = state_err(host(ud), ref, 3)
-        _say(name, calls, "state err", d, "t", host(t)[0], tref)
+        d = state_err(host(ud), ref, dim)
+        _say(name, cells, polydeg, calls, "state err", d, "t", host(t)[0], tref)
         assert np.all(d <= 1e-12), (calls, d)
         np.testing.assert_allclose(host(t)[0], tref, rtol=1e-13)
 
