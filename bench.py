@@ -228,6 +228,8 @@ def main():
     ap.add_argument("--workload", default="tgv_32")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-measured-peaks", action="store_true",
+                    help="skip the HBM copy and FP64 FMA probes (dgx_measure_peak)")
     ap.add_argument("--variants", default="rhs,mixed,batched,sedov,weak,curved,mhd,dwave",
                     help="comma list of extra variants: rhs, mixed, batched, sedov, weak, "
                          "curved, mhd, dwave ('' for none)")
@@ -293,6 +295,14 @@ def main():
                           f"after the timed repetitions",
                 "alg_bytes_per_launch": alg_bytes}
     valu = valu_object(stored_pmc(pkey), avg_ms)
+    # the board's own peaks beside the published ones (the roofline divides by the latter)
+    measured = None if args.no_measured_peaks else measured_peaks(dgx)
+    if measured and "error" not in measured:
+        roofline["measured_peak"] = measured["hbm_copy_GBs"]
+        roofline["frac_of_measured"] = round(achieved / measured["hbm_copy_GBs"], 4)
+        if valu:
+            valu["measured_peak"] = measured["fp64_fma_TFLOPs"]
+            valu["frac_of_measured"] = round(valu["achieved"] / measured["fp64_fma_TFLOPs"], 4)
     _log(f"step: {secs / args.steps * 1e3:.4f} ms/step (min of {REPS}; median "
          f"{secs_med / args.steps * 1e3:.4f}), {value:.4e} DOF-RHS/s; {kname} avg "
          f"{avg_ms * 1e3:.2f} us over {launches} launches")
@@ -308,6 +318,7 @@ def main():
                       "elements": s.E, "polydeg": 3, "dof_per_var": nodes,
                       "parallelism": "single GPU"},
            "pid_s": 1.0 / value, "roofline": roofline, "valu_fp64": valu,
+           "measured_peaks": measured,
            # unique two-point volume fluxes per node and RHS: 3N/2 in 3D (4.5 at N = 3)
            "unique_flux_evals_per_s": value * 1.5 * cfg["polydeg"]}
 
@@ -573,6 +584,20 @@ def kernel_source_hash():
             h.update(os.path.basename(f).encode())
             h.update(open(f, "rb").read())
     return h.hexdigest()
+
+
+def measured_peaks(dgx):
+    """dgx_measure_peak on this board: the copy bandwidth of a 2 GiB float64 buffer (GB/s,
+    read + written) and the FP64 vector FMA rate (TFLOP/s), each the best of 10 launches."""
+    try:
+        out = {k: round(dgx.measure_peak(k), 2) for k in ("hbm_copy_GBs", "fp64_fma_TFLOPs")}
+    except Exception as e:  # a failing probe must not hide the main line
+        return {"error": str(e)}
+    out["method"] = ("dgx_measure_peak: a grid-stride copy of 2 GiB (four 16-byte non-temporal loads in flight per lane), and "
+                     "eight independent FP64 FMA chains per lane at 8 waves per SIMD; best of 10")
+    _log(f"measured peaks: HBM copy {out['hbm_copy_GBs']:.0f} GB/s, FP64 FMA "
+         f"{out['fp64_fma_TFLOPs']:.1f} TFLOP/s")
+    return out
 
 
 def valu_object(pmc, avg_ms):

@@ -281,6 +281,21 @@ dgx_status dgx_batch_shape(dgx_batch b, int32_t *block, int32_t *grid);
 dgx_status dgx_batch_check(dgx_batch b, int32_t *flag);
 const char *dgx_batch_last_error(dgx_batch b);
 
+/* ---- measured peaks of the board (a measurement aid for rooflines, not a step of the
+ * method; the paper reports throughput, Section 3.1, and the published MI355X peaks are
+ * what a roofline divides by, these measured ones stand beside them) ---- */
+enum {
+  DGX_PEAK_HBM_COPY = 0,   /* GB/s read + written by a copy of a 2 GiB float64 buffer */
+  DGX_PEAK_FP64_FMA = 1    /* TFLOP/s of independent FP64 vector FMA chains on every lane
+                              (2 flops per FMA, 8 waves per SIMD) */
+};
+/* Runs the probe `kind` on HIP device `device` (best of 10 launches timed with HIP events,
+ * after one warm-up launch) and writes the rate to the HOST double *value.  Unlike the
+ * other calls it blocks: it allocates its buffers (4 GiB for the copy), creates its own
+ * stream, synchronises and frees everything before it returns; no handle is needed.
+ * DGX_EINVAL for a NULL value, an unknown kind or device; DGX_ENOMEM, DGX_EHIP. */
+dgx_status dgx_measure_peak(int32_t device, int32_t kind, double *value);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,7 +27,7 @@ EXPORTS = ["dgx_create", "dgx_destroy", "dgx_set_stream", "dgx_num_nodes", "dgx_
            "dgx_profile_read", "dgx_batch_create", "dgx_batch_destroy", "dgx_batch_num_nodes",
            "dgx_batch_step", "dgx_batch_rhs", "dgx_batch_tune", "dgx_batch_set_shape", "dgx_batch_shape",
            "dgx_batch_check", "dgx_batch_last_error", "dgx_create_curved", "dgx_geometry",
-           "dgx_create_mhd"]
+           "dgx_create_mhd", "dgx_measure_peak"]
 
 
 class DgxError(RuntimeError):
@@ -104,6 +104,7 @@ def lib():
             "dgx_create_curved": ([C.POINTER(CurvConfig), vp, C.POINTER(vp)], C.c_int),
             "dgx_geometry": ([vp, vp, vp], C.c_int),
             "dgx_create_mhd": ([C.POINTER(MhdConfig), vp, C.POINTER(vp)], C.c_int),
+            "dgx_measure_peak": ([C.c_int32, C.c_int32, dp], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -111,6 +112,20 @@ def lib():
             f.restype = res
         _lib = L
     return _lib
+
+
+PEAK_KINDS = {"hbm_copy_GBs": 0, "fp64_fma_TFLOPs": 1}
+
+
+def measure_peak(kind, device=None):
+    """dgx_measure_peak: the measured HBM copy bandwidth (GB/s) or FP64 FMA rate (TFLOP/s)
+    of a device (default: torch's current one); blocks while it runs."""
+    dev = torch.cuda.current_device() if device is None else int(device)
+    v = C.c_double(0.0)
+    st = lib().dgx_measure_peak(C.c_int32(dev), C.c_int32(PEAK_KINDS[kind]), C.byref(v))
+    if st != 0:
+        raise RuntimeError(f"dgx_measure_peak({kind}) failed with status {st}")
+    return v.value
 
 
 def make_config(dim, polydeg, cells, xmin, xmax, gamma=1.4, volume="ec", surface="llf",

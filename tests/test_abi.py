@@ -129,3 +129,12 @@ def test_null_handle_calls_fail_cleanly():
     assert L.dgx_rhs(None, None, None, C.c_double(0.0)) == 1
     assert L.dgx_destroy(None) == 1
     assert L.dgx_num_nodes(None) == -1
+
+
+def test_measure_peak_rejects_bad_arguments_on_host():
+    """dgx_measure_peak checks its arguments before any HIP call."""
+    L = dgx.lib()
+    v = C.c_double(0.0)
+    assert L.dgx_measure_peak(0, 0, None) == 1
+    assert L.dgx_measure_peak(0, 2, C.byref(v)) == 1
+    assert L.dgx_measure_peak(0, -1, C.byref(v)) == 1
