@@ -520,10 +520,11 @@ struct StageArgs {
   const double* dt_from = nullptr;
   int64_t dt_np = 0;
   int64_t dt_stride = 1;   // dt_from holds its values dt_stride doubles apart
-  // Large meshes: the last stage folds each element's wave speed into the DT_SLOTS slots
-  // of speed_slots (an atomic max on the bits of a positive double, slot e % DT_SLOTS), the
-  // next step's first stage reduces them (dt_from, dt_np = DT_SLOTS, dt_stride =
-  // DT_SLOT_STRIDE), and block 0 of its second stage clears them (slots_clear).
+  // Mid-size Cartesian meshes (api.hip's stage_slots): the last stage folds each element's
+  // wave speed into the DT_SLOTS slots of speed_slots (an atomic max on the bits of a
+  // positive double, slot e % DT_SLOTS), the next step's first stage reduces them (dt_from,
+  // dt_np = DT_SLOTS, dt_stride = DT_SLOT_STRIDE), and block 0 of its second stage clears
+  // them (slots_clear).
   double* speed_slots = nullptr;
   double* slots_clear = nullptr;
   double dt_cfl = 0.0, dt_n1 = 0.0;
