@@ -18,7 +18,6 @@ the roofline of the dominant kernel and the oracle on the host.
 """
 import argparse
 import json
-import math
 import os
 import statistics
 import sys

@@ -6,7 +6,6 @@ Each run is checked against the oracle (1e-12 in the flux-scale norm) and bitwis
 the single-run path, which computes every element with the same stage body.  Graph replays
 are interleaved with eager work and synchronisations and every replay is checked.
 """
-import math
 
 import numpy as np
 import pytest

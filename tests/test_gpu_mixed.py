@@ -18,11 +18,9 @@ float32 it was 3e-6 at N = 3 and 1.4e-5 at N = 7).  The log means' float32 serie
 extends to z^2 < 1e-2 (truncation 1.1e-9), which keeps the float32 logarithm away from
 b/a near 1.
 """
-import math
 
 import numpy as np
 import pytest
-import torch
 
 import oracle
 from paper_2108_06476_amd import dgx, inputs
