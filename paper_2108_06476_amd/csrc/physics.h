@@ -289,7 +289,7 @@ __device__ __forceinline__ void central_flux(const double (&uL)[DIM + 2], const 
 template <int DIM, int D>
 __device__ __forceinline__ double llf_flux(const double (&uL)[DIM + 2], const Prim<double>& L,
                                            const double (&uR)[DIM + 2], const Prim<double>& R,
-                                           double gamma, double (&f)[DIM + 2]) {
+                                           double /*gamma: in the primitives*/, double (&f)[DIM + 2]) {
   double fL[DIM + 2], fR[DIM + 2];
   phys_flux<DIM, D>(uL, L, fL);
   phys_flux<DIM, D>(uR, R, fR);
@@ -305,7 +305,7 @@ __device__ __forceinline__ double llf_flux(const double (&uL)[DIM + 2], const Pr
 template <int DIM, int D>
 __device__ __forceinline__ double hll_flux(const double (&uL)[DIM + 2], const Prim<double>& L,
                                            const double (&uR)[DIM + 2], const Prim<double>& R,
-                                           double gamma, double (&f)[DIM + 2]) {
+                                           double /*gamma: in the primitives*/, double (&f)[DIM + 2]) {
   double fL[DIM + 2], fR[DIM + 2];
   phys_flux<DIM, D>(uL, L, fL);
   phys_flux<DIM, D>(uR, R, fR);
