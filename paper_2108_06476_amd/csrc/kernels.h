@@ -1151,9 +1151,8 @@ __global__ __launch_bounds__(256) void k_smooth(const double* __restrict__ ar,
 
 // --------------------------------------------------------------------------------------
 // Max of p[0, n) over one block of T threads (T a multiple of 64), valid in thread 0.
-// The pass reads a few hundred KB from a single CU, written by every XCD just before, so it
-// is bound by load latency, not bandwidth: up to 32 T values every load is issued at once
-// (one round trip), beyond that eight per thread are kept in flight.  max is exact, so the
+// Eight independent loads per thread are kept in flight: the pass reads a few hundred KB
+// from a single CU, so it is bound by load latency, not bandwidth.  max is exact, so the
 // result does not depend on the order.  s: LDS scratch of T / 64 doubles.
 // --------------------------------------------------------------------------------------
 template <int T>
@@ -1161,22 +1160,11 @@ __device__ double block_max(const double* __restrict__ p, int64_t n, double* s) 
   static_assert(T % 64 == 0 && T <= 4096, "block of whole waves");
   double m[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int64_t i = threadIdx.x;
-  if (n <= 32 * (int64_t)T) {   // uniform
-    double v[32];
+  for (; i + 7 * T < n; i += 8 * T) {
 #pragma unroll
-    for (int k = 0; k < 32; ++k) {
-      const int64_t j = i + (int64_t)k * T;
-      v[k] = j < n ? p[j] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < 32; ++k) m[k & 7] = fmax(m[k & 7], v[k]);
-  } else {
-    for (; i + 7 * T < n; i += 8 * T) {
-#pragma unroll
-      for (int k = 0; k < 8; ++k) m[k] = fmax(m[k], p[i + k * T]);
-    }
-    for (; i < n; i += T) m[0] = fmax(m[0], p[i]);
+    for (int k = 0; k < 8; ++k) m[k] = fmax(m[k], p[i + k * T]);
   }
+  for (; i < n; i += T) m[0] = fmax(m[0], p[i]);
   double r = fmax(fmax(fmax(m[0], m[1]), fmax(m[2], m[3])), fmax(fmax(m[4], m[5]), fmax(m[6], m[7])));
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) r = fmax(r, __shfl_xor(r, o));
